@@ -1,0 +1,175 @@
+/*
+ * bsmm -- block-sparse matrix multiply for AMD MI355X (gfx950).
+ *
+ * C-ABI of the node-local multiply of the DBCSR method (Bethune et al.,
+ * "Porting of the DBCSR library for Sparse Matrix-Matrix Multiplications to
+ * Intel Xeon Phi systems", 2017, Section 2): blocked-CSR matrices made of
+ * small dense blocks, C = alpha*A*B + beta*C built from pairwise block
+ * products, with the on-the-fly norm filter.
+ *
+ * Conventions for every entry point:
+ *   - No exception or abort crosses this boundary; every call returns a
+ *     bsmm_status and, on failure, bsmm_last_error() describes it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it in order.  Calls that must report sizes to the
+ *     host synchronise that stream and say so below.
+ *   - Handles are not thread-safe; do not use one handle from two threads at
+ *     once.  Distinct handles may be used concurrently on distinct streams.
+ *   - Block values are FP64, each block stored row-major, blocks contiguous
+ *     in CSR order (block b of row i has row_sizes[i] x col_sizes[col_idx[b]]
+ *     values).  Block sizes are >= 1.
+ *   - The library owns all device memory behind a handle and frees it in
+ *     bsmm_destroy().  Buffers passed in are only read during the call
+ *     (create) or only written (norms, export); the caller keeps ownership.
+ */
+#ifndef BSMM_H
+#define BSMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsmm_matrix* bsmm_mat;
+
+typedef enum {
+  BSMM_OK = 0,
+  BSMM_E_ARG = 1,          /* NULL handle/pointer, bad size, non-finite scalar, unknown enum */
+  BSMM_E_SHAPE = 2,        /* block sizes of the operands do not conform */
+  BSMM_E_PATTERN = 3,      /* row_ptr not monotone / wrong ends, column out of range,
+                              columns not strictly increasing in a row */
+  BSMM_E_ALIAS = 4,        /* output handle is also an input operand (A or B) */
+  BSMM_E_NOMEM = 5,        /* device or host allocation failed */
+  BSMM_E_CAPACITY = 6,     /* a result exceeds int32 block indexing or a reserved capacity */
+  BSMM_E_HIP = 7,          /* a HIP runtime call failed */
+  BSMM_E_UNSUPPORTED = 8   /* valid input outside what this build handles (message says why) */
+} bsmm_status;
+
+/* Arithmetic of the block products. */
+typedef enum {
+  BSMM_FP64 = 0 /* FP64 products and accumulation */
+} bsmm_prec;
+
+enum { BSMM_PTR_HOST = 0, BSMM_PTR_DEVICE = 1 };
+
+/* Counters of the last multiply that wrote a handle. */
+typedef struct {
+  int64_t candidates;  /* block products with both blocks present (before the filter) */
+  int64_t products;    /* block products kept by the filter and computed */
+  int64_t nnzb;        /* blocks in the result */
+  int64_t nvals;       /* values in the result */
+  double useful_flops; /* sum over kept products of 2*m*n*k */
+} bsmm_mult_stats;
+
+/*
+ * Create a matrix from blocked CSR (Section 2, storage format).
+ *   nbrows, nbcols      : block rows / block columns (>= 0)
+ *   row_sizes[nbrows]   : rows of each block row (>= 1); always host memory
+ *   col_sizes[nbcols]   : columns of each block column (>= 1); always host memory
+ *   nnzb                : stored blocks
+ *   row_ptr[nbrows+1]   : row_ptr[0] = 0, non-decreasing, row_ptr[nbrows] = nnzb
+ *   col_idx[nnzb]       : block columns, strictly increasing within a row
+ *   values              : all block values (see conventions); NULL = all zero
+ *   ptr_kind            : BSMM_PTR_HOST or BSMM_PTR_DEVICE for row_ptr/col_idx/values
+ * The inputs are copied and validated (device inputs are copied to the host
+ * for validation, which synchronises `stream`).  On error *out is untouched.
+ */
+bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int32_t* row_sizes,
+                        const int32_t* col_sizes, int32_t nnzb, const int32_t* row_ptr,
+                        const int32_t* col_idx, const double* values, int ptr_kind, void* stream);
+
+/* Release a handle and its device memory (synchronises the device first). NULL is a no-op. */
+bsmm_status bsmm_destroy(bsmm_mat m);
+
+/*
+ * C_out = alpha * A * B + beta * C_in, with the on-the-fly filter
+ * (Section 2): the product of blocks A(i,k) and B(k,j) is performed only if
+ * filter_eps <= 0 or fl(|A(i,k)|_F * |B(k,j)|_F) > filter_eps.
+ *   - The result pattern is every (i,j) with at least one performed product,
+ *     plus the pattern of C_in when beta != 0.  Blocks are kept even if zero.
+ *   - C_in may be NULL (no old values), may be C_out (in-place update) and
+ *     may be A or B.  With beta == 0 it is never read.
+ *   - C_out must not be A or B (BSMM_E_ALIAS).  Its previous pattern and
+ *     values are replaced.  A.col_sizes must equal B.row_sizes, and C_out
+ *     (and C_in when read) must have A's row sizes and B's column sizes
+ *     (BSMM_E_SHAPE).
+ *   - alpha, beta and filter_eps must be finite (BSMM_E_ARG).
+ *   - Synchronises `stream` once, after the symbolic phase, to size C_out.
+ * On error C_out is left as it was.
+ */
+bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in,
+                          bsmm_mat C_out, double filter_eps, int prec, void* stream);
+
+/*
+ * Drop every block whose Frobenius norm is not above eps (eps <= 0 keeps
+ * all blocks); compacts the pattern and values in place (Section 2: the
+ * filter "increases sparsity").  Synchronises `stream` to read the new size.
+ */
+bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream);
+
+/*
+ * Frobenius norm of every stored block, in CSR order, into out[nnzb]
+ * (device memory owned by the caller).  The sum of squares runs in a fixed
+ * order (64 interleaved partial sums with fused multiply-add, then a pairwise
+ * tree, then a correctly rounded square root), so the values are bitwise
+ * reproducible.
+ */
+bsmm_status bsmm_norms(bsmm_mat m, double* out, void* stream);
+
+/* Sizes of a matrix (any pointer may be NULL).  Host-side metadata, no sync. */
+bsmm_status bsmm_info(bsmm_mat m, int32_t* nbrows, int32_t* nbcols, int32_t* nnzb, int64_t* nvals);
+
+/*
+ * Copy the pattern and values out: row_ptr[nbrows+1], col_idx[nnzb],
+ * values[nvals] (any pointer may be NULL), host or device memory per
+ * ptr_kind.  Synchronises `stream`.
+ */
+bsmm_status bsmm_export(bsmm_mat m, int32_t* row_ptr, int32_t* col_idx, double* values, int ptr_kind,
+                        void* stream);
+
+/*
+ * Product stack of the last multiply that wrote C: one entry per performed
+ * block product, (C block, A block, B block) indices in CSR order, sorted by
+ * C block and then by the inner block index k.  *nprod receives the count;
+ * the arrays (any may be NULL) must hold that many entries.  Synchronises.
+ */
+bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t* st_b, int64_t* nprod,
+                              int ptr_kind, void* stream);
+
+/* Counters of the last multiply that wrote C (zeros if none). */
+bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
+
+/* Phases timed by bsmm_timing / bsmm_phase_times. */
+enum {
+  BSMM_PHASE_NORMS = 0,    /* block norms of A and B (only when filter_eps > 0) */
+  BSMM_PHASE_COUNT = 1,    /* symbolic count pass and row scans */
+  BSMM_PHASE_SIZING = 2,   /* read-back of the result size and output allocation */
+  BSMM_PHASE_FILL = 3,     /* symbolic fill pass: pattern and product stack */
+  BSMM_PHASE_NUMERIC = 4,  /* batched block products and alpha/beta finalisation */
+  BSMM_PHASE_TOTAL = 5,    /* whole multiply, first to last enqueued operation */
+  BSMM_NPHASES = 6
+};
+
+/*
+ * Start (enable != 0) or stop recording HIP events around the phases of every
+ * multiply that writes C, on the multiply's own stream.  Starting clears
+ * earlier records.  Recording adds no synchronisation.
+ */
+bsmm_status bsmm_timing(bsmm_mat C, int enable);
+
+/*
+ * Sum of each phase's duration in milliseconds over the multiplies recorded
+ * since bsmm_timing(C, 1): ms[BSMM_NPHASES]; *count receives the number of
+ * recorded multiplies.  Synchronises on the recorded events.
+ */
+bsmm_status bsmm_phase_times(bsmm_mat C, double* ms, int64_t* count);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* bsmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSMM_H */

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libbsmm (see include/bsmm.h).
+
+Argument marshalling only: every step of the multiply runs in the HIP library.
+The functions carry the C names; each raises BsmmError on a non-OK status.
+Host arrays are numpy arrays; device arrays are torch tensors on a ROCm
+device, which is also where streams come from.
+
+If libbsmm.so has not been built, loading fails loudly: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsmm.so")
+
+BSMM_OK = 0
+STATUS_NAMES = {0: "BSMM_OK", 1: "BSMM_E_ARG", 2: "BSMM_E_SHAPE", 3: "BSMM_E_PATTERN", 4: "BSMM_E_ALIAS",
+                5: "BSMM_E_NOMEM", 6: "BSMM_E_CAPACITY", 7: "BSMM_E_HIP", 8: "BSMM_E_UNSUPPORTED"}
+BSMM_FP64 = 0
+BSMM_PTR_HOST = 0
+BSMM_PTR_DEVICE = 1
+
+
+class BsmmError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS_NAMES.get(code, str(code))
+
+
+class MultStats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("products", ctypes.c_int64), ("nnzb", ctypes.c_int64),
+                ("nvals", ctypes.c_int64), ("useful_flops", ctypes.c_double)]
+
+
+# every function declared in include/bsmm.h, with its ctypes signature
+_vp, _i32, _i64, _dbl, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+SIGNATURES = {
+    "bsmm_create": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _int, _vp], _int),
+    "bsmm_destroy": ([_vp], _int),
+    "bsmm_multiply": ([_dbl, _vp, _vp, _dbl, _vp, _vp, _dbl, _int, _vp], _int),
+    "bsmm_filter": ([_vp, _dbl, _vp], _int),
+    "bsmm_norms": ([_vp, _vp, _vp], _int),
+    "bsmm_info": ([_vp, _vp, _vp, _vp, _vp], _int),
+    "bsmm_export": ([_vp, _vp, _vp, _vp, _int, _vp], _int),
+    "bsmm_export_stack": ([_vp, _vp, _vp, _vp, _vp, _int, _vp], _int),
+    "bsmm_stats": ([_vp, _vp], _int),
+    "bsmm_timing": ([_vp, _int], _int),
+    "bsmm_phase_times": ([_vp, _vp, _vp], _int),
+    "bsmm_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libbsmm.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1708_03604_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(fn, rc):
+    if rc != BSMM_OK:
+        raise BsmmError(rc, fn, lib().bsmm_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return getattr(stream, "cuda_stream", stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+def _addr(x):
+    """(address, kind) of a numpy array (host) or a torch tensor (its device)."""
+    if x is None:
+        return None, BSMM_PTR_HOST
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be contiguous")
+        return (x.ctypes.data if x.size else None), BSMM_PTR_HOST
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return (x.data_ptr() if x.numel() else None), (BSMM_PTR_DEVICE if x.is_cuda else BSMM_PTR_HOST)
+    raise TypeError(type(x))
+
+
+# ------------------------------------------------------------ C functions
+
+def bsmm_create(nbrows, nbcols, row_sizes, col_sizes, nnzb, row_ptr, col_idx, values, ptr_kind=None,
+                stream=None):
+    rs = np.ascontiguousarray(row_sizes, dtype=np.int32)
+    cs = np.ascontiguousarray(col_sizes, dtype=np.int32)
+    prp, k1 = _addr(row_ptr)
+    pci, k2 = _addr(col_idx)
+    pv, k3 = _addr(values)
+    if ptr_kind is None:
+        ptr_kind = k1
+    h = ctypes.c_void_p()
+    rc = lib().bsmm_create(ctypes.byref(h), int(nbrows), int(nbcols), rs.ctypes.data if rs.size else None,
+                           cs.ctypes.data if cs.size else None, int(nnzb), prp, pci, pv, int(ptr_kind),
+                           _stream(stream))
+    _check("bsmm_create", rc)
+    return h
+
+
+def bsmm_destroy(h):
+    _check("bsmm_destroy", lib().bsmm_destroy(h))
+
+
+def bsmm_multiply(alpha, A, B, beta, C_in, C_out, filter_eps, prec=BSMM_FP64, stream=None):
+    rc = lib().bsmm_multiply(float(alpha), A, B, float(beta), C_in, C_out, float(filter_eps), int(prec),
+                             _stream(stream))
+    _check("bsmm_multiply", rc)
+
+
+def bsmm_filter(M, eps, stream=None):
+    _check("bsmm_filter", lib().bsmm_filter(M, float(eps), _stream(stream)))
+
+
+def bsmm_norms(M, out, stream=None):
+    p, _ = _addr(out)
+    _check("bsmm_norms", lib().bsmm_norms(M, p, _stream(stream)))
+
+
+def bsmm_info(M):
+    nbr, nbc, nnzb, nv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check("bsmm_info", lib().bsmm_info(M, ctypes.byref(nbr), ctypes.byref(nbc), ctypes.byref(nnzb),
+                                         ctypes.byref(nv)))
+    return nbr.value, nbc.value, nnzb.value, nv.value
+
+
+def bsmm_export(M, row_ptr, col_idx, values, ptr_kind=None, stream=None):
+    a, k = _addr(row_ptr)
+    b, _ = _addr(col_idx)
+    c, _ = _addr(values)
+    _check("bsmm_export", lib().bsmm_export(M, a, b, c, int(k if ptr_kind is None else ptr_kind),
+                                             _stream(stream)))
+
+
+def bsmm_export_stack(C, st_c, st_a, st_b, ptr_kind=None, stream=None):
+    a, k = _addr(st_c)
+    b, _ = _addr(st_a)
+    c, _ = _addr(st_b)
+    n = ctypes.c_int64()
+    _check("bsmm_export_stack", lib().bsmm_export_stack(C, a, b, c, ctypes.byref(n),
+                                                         int(k if ptr_kind is None else ptr_kind),
+                                                         _stream(stream)))
+    return n.value
+
+
+def bsmm_stats(C):
+    s = MultStats()
+    _check("bsmm_stats", lib().bsmm_stats(C, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in MultStats._fields_}
+
+
+PHASES = ("norms", "count", "sizing", "fill", "numeric", "total")
+
+
+def bsmm_timing(C, enable):
+    _check("bsmm_timing", lib().bsmm_timing(C, int(enable)))
+
+
+def bsmm_phase_times(C):
+    ms = np.zeros(len(PHASES), dtype=np.float64)
+    n = ctypes.c_int64()
+    _check("bsmm_phase_times", lib().bsmm_phase_times(C, ms.ctypes.data, ctypes.byref(n)))
+    return dict(zip(PHASES, ms.tolist())), n.value
+
+
+def bsmm_last_error():
+    return lib().bsmm_last_error().decode()
+
+
+# ------------------------------------------------------------ convenience
+
+class Matrix:
+    """Owning wrapper of a bsmm_mat handle."""
+
+    def __init__(self, handle, row_sizes, col_sizes):
+        self.handle = handle
+        self.row_sizes = np.ascontiguousarray(row_sizes, dtype=np.int32)
+        self.col_sizes = np.ascontiguousarray(col_sizes, dtype=np.int32)
+
+    @classmethod
+    def from_csr(cls, M, stream=None):
+        """Upload a host block-CSR matrix (attributes row_sizes, col_sizes,
+        row_ptr, col_idx, values)."""
+        rp = np.ascontiguousarray(M.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(M.col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(M.values, dtype=np.float64)
+        h = bsmm_create(len(M.row_sizes), len(M.col_sizes), M.row_sizes, M.col_sizes, len(ci), rp, ci, v,
+                        BSMM_PTR_HOST, stream)
+        return cls(h, M.row_sizes, M.col_sizes)
+
+    @classmethod
+    def empty(cls, row_sizes, col_sizes, stream=None):
+        rp = np.zeros(len(row_sizes) + 1, dtype=np.int32)
+        h = bsmm_create(len(row_sizes), len(col_sizes), row_sizes, col_sizes, 0, rp, None, None, BSMM_PTR_HOST,
+                        stream)
+        return cls(h, row_sizes, col_sizes)
+
+    def info(self):
+        return bsmm_info(self.handle)
+
+    def to_host(self, stream=None):
+        """(row_ptr, col_idx, values) as numpy arrays."""
+        nbr, _, nnzb, nv = self.info()
+        rp = np.zeros(nbr + 1, dtype=np.int32)
+        ci = np.zeros(max(nnzb, 1), dtype=np.int32)
+        v = np.zeros(max(nv, 1), dtype=np.float64)
+        bsmm_export(self.handle, rp, ci if nnzb else None, v if nv else None, BSMM_PTR_HOST, stream)
+        return rp, ci[:nnzb], v[:nv]
+
+    def stack(self, stream=None):
+        n = bsmm_export_stack(self.handle, None, None, None, BSMM_PTR_HOST, stream)
+        out = np.zeros((3, max(n, 1)), dtype=np.int32)
+        bsmm_export_stack(self.handle, out[0], out[1], out[2], BSMM_PTR_HOST, stream)
+        return np.ascontiguousarray(out[:, :n].T)
+
+    def close(self):
+        if self.handle is not None:
+            bsmm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def multiply(alpha, A, B, beta, C_in, C_out, eps, prec=BSMM_FP64, stream=None):
+    bsmm_multiply(alpha, A.handle, B.handle, beta, C_in.handle if C_in is not None else None, C_out.handle, eps,
+                  prec, stream)

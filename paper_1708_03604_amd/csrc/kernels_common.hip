@@ -1,0 +1,209 @@
+// Block norms, device-wide exclusive scans and the block filter.
+//
+// Norm order (matches the documented reading of the filter in Section 2 of the
+// paper): lane l of a wave sums x_e^2 for e = l, l+64, ... with fused
+// multiply-add, then partial l += partial l+d for d = 32..1, then a correctly
+// rounded square root.
+#include "bsmm_internal.h"
+
+namespace bsmm {
+
+// ---------------------------------------------------------------- norms
+
+__global__ __launch_bounds__(256) void k_block_norms(const int64_t* __restrict__ blk_off,
+                                                     const double* __restrict__ values, int32_t nnzb,
+                                                     double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int32_t nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int32_t b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nnzb; b += nwaves) {
+    const int64_t o = blk_off[b];
+    const int64_t n = blk_off[b + 1] - o;
+    const double* x = values + o;
+    double p = 0.0;
+    for (int64_t e = lane; e < n; e += 64) p = fma(x[e], x[e], p);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const double other = __shfl_down(p, d, 64);
+      if (lane < d) p = p + other;
+    }
+    if (lane == 0) out[b] = sqrt(p);
+  }
+}
+
+hipError_t launch_block_norms(const int64_t* blk_off, const double* values, int32_t nnzb, double* out,
+                              hipStream_t s) {
+  if (nnzb <= 0) return hipSuccess;
+  int32_t blocks = (nnzb + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_block_norms, dim3(blocks), dim3(256), 0, s, blk_off, values, nnzb, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scans
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+// Exclusive scan of v over the workgroup; *total gets the workgroup sum.
+__device__ int64_t wg_exclusive_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partial(const int64_t* __restrict__ in, int64_t n,
+                                                               int64_t* __restrict__ partial) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  int64_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    const int64_t i = base + (int64_t)u * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  int64_t tot;
+  wg_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Single workgroup: exclusive scan of the chunk sums in place; partial[nchunks] = total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t* __restrict__ partial, int64_t nchunks) {
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nchunks; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nchunks ? partial[i] : 0;
+    int64_t tot;
+    const int64_t ex = wg_exclusive_scan(v, &tot);
+    if (i < nchunks) partial[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partial[nchunks] = carry;
+}
+
+// out[i] = sum of in[0..i), out[n] = total; each thread owns kScanItems consecutive items.
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const int64_t* __restrict__ in, int64_t n,
+                                                             const int64_t* __restrict__ partial,
+                                                             int64_t* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    v[u] = (base + u < n) ? in[base + u] : 0;
+    s += v[u];
+  }
+  int64_t tot;
+  int64_t run = partial[blockIdx.x] + wg_exclusive_scan(s, &tot);
+#pragma unroll
+  for (int u = 0; u < kScanItems; ++u) {
+    if (base + u < n) out[base + u] = run;
+    run += v[u];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[gridDim.x];
+}
+
+__global__ void k_zero_i64(int64_t* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
+// Device-wide exclusive scan: out[0..n] (n+1 entries), out[n] = total.
+// tmp needs scan_tmp_elems(n) int64 entries.  in and out must not overlap.
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 2; }
+
+hipError_t scan_exclusive(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s) {
+  const int64_t nchunks = (n + kScanChunk - 1) / kScanChunk;
+  if (nchunks == 0) {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s, tmp, nchunks);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, in, n, tmp, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- filter
+
+// keep[b] = 1 if eps <= 0 or norm > eps; vsz[b] = its value count if kept.
+__global__ __launch_bounds__(256) void k_filter_flags(const int64_t* __restrict__ blk_off,
+                                                      const double* __restrict__ norms, int32_t nnzb,
+                                                      double eps, int64_t* __restrict__ keep,
+                                                      int64_t* __restrict__ vsz) {
+  const int32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nnzb) return;
+  const bool k = (eps <= 0.0) || (norms[b] > eps);
+  keep[b] = k ? 1 : 0;
+  vsz[b] = k ? (blk_off[b + 1] - blk_off[b]) : 0;
+}
+
+// One wave per source block: copy kept blocks to their compacted position.
+__global__ __launch_bounds__(256) void k_filter_compact(int32_t nnzb, const int64_t* __restrict__ keep_pos,
+                                                        const int64_t* __restrict__ voff,
+                                                        const int32_t* __restrict__ col_idx,
+                                                        const int64_t* __restrict__ blk_off,
+                                                        const double* __restrict__ values,
+                                                        int32_t* __restrict__ out_col_idx,
+                                                        int64_t* __restrict__ out_blk_off,
+                                                        double* __restrict__ out_values) {
+  const int lane = threadIdx.x & 63;
+  const int32_t nwaves = gridDim.x * 4;
+  for (int32_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nnzb; b += nwaves) {
+    const int64_t pos = keep_pos[b];
+    if (keep_pos[b + 1] == pos) continue;  // dropped
+    const int64_t src = blk_off[b], n = blk_off[b + 1] - src, dst = voff[b];
+    if (lane == 0) {
+      out_col_idx[pos] = col_idx[b];
+      out_blk_off[pos] = dst;
+    }
+    for (int64_t e = lane; e < n; e += 64) out_values[dst + e] = values[src + e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out_blk_off[keep_pos[nnzb]] = voff[nnzb];
+}
+
+__global__ __launch_bounds__(256) void k_filter_rowptr(int32_t nbrows, const int32_t* __restrict__ row_ptr,
+                                                       const int64_t* __restrict__ keep_pos,
+                                                       int32_t* __restrict__ out_row_ptr) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i <= nbrows) out_row_ptr[i] = (int32_t)keep_pos[row_ptr[i]];
+}
+
+hipError_t launch_filter(const int32_t* row_ptr, const int32_t* col_idx, const int64_t* blk_off,
+                         const double* values, int32_t nbrows, int32_t nnzb, const double* norms, double eps,
+                         int64_t* keep, int64_t* vsz, int64_t* keep_pos, int64_t* voff, int64_t* tmp,
+                         int32_t* out_row_ptr, int32_t* out_col_idx, int64_t* out_blk_off,
+                         double* out_values, hipStream_t s) {
+  if (nnzb > 0) {
+    hipLaunchKernelGGL(k_filter_flags, dim3((nnzb + 255) / 256), dim3(256), 0, s, blk_off, norms, nnzb, eps,
+                       keep, vsz);
+  }
+  hipError_t e = scan_exclusive(keep, nnzb, keep_pos, tmp, s);
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(vsz, nnzb, voff, tmp, s);
+  if (e != hipSuccess) return e;
+  int32_t blocks = (nnzb + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_filter_compact, dim3(blocks), dim3(256), 0, s, nnzb, keep_pos, voff, col_idx, blk_off,
+                     values, out_col_idx, out_blk_off, out_values);
+  hipLaunchKernelGGL(k_filter_rowptr, dim3((nbrows + 1 + 255) / 256), dim3(256), 0, s, nbrows, row_ptr, keep_pos,
+                     out_row_ptr);
+  return hipGetLastError();
+}
+
+}  // namespace bsmm

@@ -1,0 +1,431 @@
+// Symbolic phase of the block-sparse multiply: result pattern and product
+// stack, with the on-the-fly norm filter applied to every candidate product.
+//
+// Section 2 of the paper: the local multiply loops over A block rows and, for
+// each, over the B blocks reached through A's columns; a block product is kept
+// only if the product of the two block norms exceeds the threshold.  Here one
+// workgroup owns one C block row i.  The candidates (A(i,k), B(k,j)) of the
+// row are enumerated as a flat index over the concatenated B rows, so all 256
+// lanes stay busy even when B rows are short.  Kept candidates are merged by
+// block column in an LDS open-addressing hash, which gives the row's distinct
+// columns and per-column product counts; ranking the columns gives the sorted
+// pattern, and a scan of the counts gives each C block's slice of the stack.
+//
+// Two passes share the enumeration: the count pass sizes the outputs, the fill
+// pass writes them.  Both take exactly the same keep/drop decisions.
+#include "bsmm_internal.h"
+
+namespace bsmm {
+
+constexpr int kHashBits = 11;
+static_assert((1 << kHashBits) == kHashSlots, "hash size");
+static_assert(kMaxRowA % kSymThreads == 0, "A chunking");
+static_assert(kMaxRowBlocks % kSymThreads == 0, "row chunking");
+
+__device__ __forceinline__ uint32_t hash_of(int32_t j) { return ((uint32_t)j * 2654435761u) >> (32 - kHashBits); }
+
+// Insert block column j; returns its slot (or -1 if the table is full).
+__device__ __forceinline__ int hash_insert(int32_t* hkey, int32_t j, bool* fresh) {
+  uint32_t h = hash_of(j);
+  for (int probe = 0; probe < kHashSlots; ++probe) {
+    const int32_t prev = atomicCAS(&hkey[h], -1, j);
+    if (prev == -1) {
+      *fresh = true;
+      return (int)h;
+    }
+    if (prev == j) {
+      *fresh = false;
+      return (int)h;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  *fresh = false;
+  return -1;
+}
+
+__device__ __forceinline__ int hash_find(const int32_t* hkey, int32_t j) {
+  uint32_t h = hash_of(j);
+  for (int probe = 0; probe < kHashSlots; ++probe) {
+    const int32_t k = hkey[h];
+    if (k == j) return (int)h;
+    if (k == -1) return -1;
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  return -1;
+}
+
+// Exclusive scan over the workgroup (256 threads); *total receives the sum.
+__device__ int64_t sym_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t wsum[kSymThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSymThreads / 64; ++w) {
+    if (w < wave) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+// Row state in LDS common to both passes.
+struct RowA {
+  int32_t qs[kMaxRowA];        // first B block of B row k_p
+  int32_t ks[kMaxRowA];        // inner block size of k_p
+  int32_t pre[kMaxRowA + 1];   // exclusive prefix of B row lengths
+  double nrm[kMaxRowA];        // norm of A(i, k_p)
+};
+
+// Load the A entries of row i and the candidate prefix.  Returns the number of
+// candidates T (or -1 if the row is outside the supported limits).
+__device__ int32_t load_row(const SymArgs& g, int32_t i, RowA& ra, int32_t* a0_out, int32_t* na_out) {
+  const int tid = threadIdx.x;
+  const int32_t a0 = g.A.row_ptr[i];
+  const int32_t nA = g.A.row_ptr[i + 1] - a0;
+  *a0_out = a0;
+  *na_out = nA;
+  if (nA > kMaxRowA) return -1;
+  constexpr int kPer = kMaxRowA / kSymThreads;
+  int32_t len[kPer];
+  int64_t mysum = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int32_t p = tid * kPer + u;
+    len[u] = 0;
+    if (p < nA) {
+      const int32_t k = g.A.col_idx[a0 + p];
+      const int32_t qs = g.B.row_ptr[k];
+      len[u] = g.B.row_ptr[k + 1] - qs;
+      ra.qs[p] = qs;
+      ra.ks[p] = g.A.col_sizes[k];
+      ra.nrm[p] = g.use_eps ? g.normA[a0 + p] : 0.0;
+    }
+    mysum += len[u];
+  }
+  int64_t total;
+  int64_t run = sym_scan(mysum, &total);
+  if (total > 0x7fffffffLL) return -1;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int32_t p = tid * kPer + u;
+    if (p < nA) ra.pre[p] = (int32_t)run;
+    run += len[u];
+  }
+  if (tid == 0) ra.pre[nA] = (int32_t)total;
+  __syncthreads();
+  return (int32_t)total;
+}
+
+// Candidate t of the row -> (A entry p, B block q).
+__device__ __forceinline__ void candidate(const RowA& ra, int32_t nA, int32_t t, int32_t* p_out, int32_t* q_out) {
+  int lo = 0, hi = nA - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ra.pre[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  *p_out = lo;
+  *q_out = ra.qs[lo] + (t - ra.pre[lo]);
+}
+
+__device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA& ra, int32_t p, int32_t q) {
+  if (!g.use_eps) return true;
+  const double prod = ra.nrm[p] * g.normB[q];
+  return prod > g.eps;
+}
+
+// ------------------------------------------------------------------ count
+
+__global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
+  __shared__ int32_t hkey[kHashSlots];
+  __shared__ RowA ra;
+  __shared__ int32_t s_nc;
+  __shared__ unsigned long long s_sumn;
+  __shared__ unsigned long long s_np;
+  __shared__ unsigned long long s_nf;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+    for (int h = tid; h < kHashSlots; h += kSymThreads) hkey[h] = -1;
+    if (tid == 0) {
+      s_nc = 0;
+      s_sumn = 0;
+      s_np = 0;
+      s_nf = 0;
+      s_bad = 0;
+    }
+    __syncthreads();
+    int32_t a0, nA;
+    const int32_t T = load_row(g, i, ra, &a0, &nA);
+    if (T < 0) {
+      if (tid == 0) {
+        atomicOr(g.flags, kFlagRowTooManyA);
+        g.row_nc[i] = 0;
+        g.row_np[i] = 0;
+        g.row_nv[i] = 0;
+        g.row_ncand[i] = 0;
+        g.row_nf[i] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    uint32_t np = 0;
+    uint64_t nf = 0;
+    for (int32_t t = tid; t < T; t += kSymThreads) {
+      int32_t p, q;
+      candidate(ra, nA, t, &p, &q);
+      if (!keep_product(g, ra, p, q)) continue;
+      ++np;
+      const int32_t j = g.B.col_idx[q];
+      nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[p];
+      bool fresh;
+      const int h = hash_insert(hkey, j, &fresh);
+      if (h < 0) {
+        s_bad = 1;
+      } else if (fresh) {
+        atomicAdd(&s_nc, 1);
+        atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+      }
+    }
+    if (g.use_old) {
+      const int32_t o1 = g.Cin.row_ptr[i + 1];
+      for (int32_t q = g.Cin.row_ptr[i] + tid; q < o1; q += kSymThreads) {
+        const int32_t j = g.Cin.col_idx[q];
+        bool fresh;
+        const int h = hash_insert(hkey, j, &fresh);
+        if (h < 0) {
+          s_bad = 1;
+        } else if (fresh) {
+          atomicAdd(&s_nc, 1);
+          atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+        }
+      }
+    }
+    if (np) {
+      atomicAdd(&s_np, (unsigned long long)np);
+      atomicAdd(&s_nf, (unsigned long long)nf);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const bool bad = s_bad || s_nc > kMaxRowBlocks;
+      if (bad) atomicOr(g.flags, kFlagRowTooManyC);
+      g.row_nc[i] = bad ? 0 : s_nc;
+      g.row_np[i] = bad ? 0 : (int64_t)s_np;
+      g.row_nv[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_sumn;
+      g.row_ncand[i] = T;
+      g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ fill
+
+__global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
+  __shared__ int32_t hkey[kHashSlots];
+  __shared__ int32_t hcnt[kHashSlots];
+  __shared__ int32_t hold[kHashSlots];
+  __shared__ int32_t hrank[kHashSlots];
+  __shared__ RowA ra;
+  __shared__ int32_t ekey[kMaxRowBlocks];
+  __shared__ int32_t eslot[kMaxRowBlocks];
+  __shared__ int32_t spre[kMaxRowBlocks];
+  __shared__ int32_t cursor[kMaxRowBlocks];
+  __shared__ int64_t svoff[kMaxRowBlocks];
+  __shared__ int32_t s_ne;
+  const int tid = threadIdx.x;
+  constexpr int kPer = kMaxRowBlocks / kSymThreads;
+  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+    for (int h = tid; h < kHashSlots; h += kSymThreads) {
+      hkey[h] = -1;
+      hcnt[h] = 0;
+      hold[h] = -1;
+    }
+    if (tid == 0) s_ne = 0;
+    __syncthreads();
+    int32_t a0, nA;
+    const int32_t T = load_row(g, i, ra, &a0, &nA);
+    if (T < 0) continue;  // uniform over the workgroup; reported by the count pass
+    for (int32_t t = tid; t < T; t += kSymThreads) {
+      int32_t p, q;
+      candidate(ra, nA, t, &p, &q);
+      if (!keep_product(g, ra, p, q)) continue;
+      bool fresh;
+      const int h = hash_insert(hkey, g.B.col_idx[q], &fresh);
+      if (h >= 0) atomicAdd(&hcnt[h], 1);
+    }
+    if (g.use_old) {
+      const int32_t o1 = g.Cin.row_ptr[i + 1];
+      for (int32_t q = g.Cin.row_ptr[i] + tid; q < o1; q += kSymThreads) {
+        bool fresh;
+        const int h = hash_insert(hkey, g.Cin.col_idx[q], &fresh);
+        if (h >= 0) hold[h] = q;
+      }
+    }
+    __syncthreads();
+    for (int h = tid; h < kHashSlots; h += kSymThreads) {
+      if (hkey[h] >= 0) {
+        const int e = atomicAdd(&s_ne, 1);
+        if (e < kMaxRowBlocks) {
+          ekey[e] = hkey[h];
+          eslot[e] = h;
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t nC = s_ne;
+    if (nC > kMaxRowBlocks) continue;  // reported by the count pass
+    // Rank the distinct columns: rank = number of smaller columns.
+    for (int e = tid; e < nC; e += kSymThreads) {
+      const int32_t key = ekey[e];
+      int r = 0;
+      for (int e2 = 0; e2 < nC; ++e2) r += (ekey[e2] < key) ? 1 : 0;
+      hrank[eslot[e]] = r;
+    }
+    __syncthreads();
+    const int32_t crow = g.c_row_ptr[i];
+    for (int e = tid; e < nC; e += kSymThreads) {
+      const int h = eslot[e];
+      const int r = hrank[h];
+      spre[r] = hcnt[h];
+      svoff[r] = g.c_col_sizes[ekey[e]];
+      g.c_col_idx[crow + r] = ekey[e];
+      g.c_old_idx[crow + r] = hold[h];
+    }
+    __syncthreads();
+    // Scan the per-column product counts and value sizes in rank order.
+    {
+      int32_t cnt[kPer];
+      int64_t vs[kPer];
+      int64_t sc = 0, sv = 0;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int r = tid * kPer + u;
+        cnt[u] = r < nC ? spre[r] : 0;
+        vs[u] = r < nC ? svoff[r] : 0;
+        sc += cnt[u];
+        sv += vs[u];
+      }
+      int64_t tc, tv;
+      int64_t rc = sym_scan(sc, &tc);
+      int64_t rv = sym_scan(sv, &tv);
+      const int64_t prow = g.row_pstart[i];
+      const int64_t vrow = g.row_vstart[i];
+      const int64_t m = g.c_row_sizes[i];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int r = tid * kPer + u;
+        if (r < nC) {
+          spre[r] = (int32_t)rc;
+          cursor[r] = 0;
+          g.prod_ptr[crow + r] = prow + rc;
+          g.c_blk_off[crow + r] = vrow + m * rv;
+        }
+        rc += cnt[u];
+        rv += vs[u];
+      }
+    }
+    __syncthreads();
+    // Place the kept products; order inside a C block is fixed up below.
+    const int64_t prow = g.row_pstart[i];
+    for (int32_t t = tid; t < T; t += kSymThreads) {
+      int32_t p, q;
+      candidate(ra, nA, t, &p, &q);
+      if (!keep_product(g, ra, p, q)) continue;
+      const int h = hash_find(hkey, g.B.col_idx[q]);
+      const int r = hrank[h];
+      const int32_t pos = spre[r] + atomicAdd(&cursor[r], 1);
+      g.prod_a[prow + pos] = a0 + p;
+      g.prod_b[prow + pos] = q;
+    }
+    __syncthreads();
+    // Sort each C block's products by A block index (= by inner index k).
+    for (int r = tid; r < nC; r += kSymThreads) {
+      int32_t* pa = g.prod_a + prow + spre[r];
+      int32_t* pb = g.prod_b + prow + spre[r];
+      const int n = cursor[r];
+      for (int x = 1; x < n; ++x) {
+        const int32_t ka = pa[x], kb = pb[x];
+        int y = x - 1;
+        while (y >= 0 && pa[y] > ka) {
+          pa[y + 1] = pa[y];
+          pb[y + 1] = pb[y];
+          --y;
+        }
+        pa[y + 1] = ka;
+        pb[y + 1] = kb;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
+  if (a.A.nbrows <= 0) return hipSuccess;
+  const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
+  hipLaunchKernelGGL(k_sym_count, dim3(grid), dim3(kSymThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
+  if (a.A.nbrows <= 0) return hipSuccess;
+  const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
+  hipLaunchKernelGGL(k_sym_fill, dim3(grid), dim3(kSymThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// c_row_ptr (int32) from the int64 prefix of per-row block counts; closes the
+// product and value offset arrays with their totals.
+__global__ __launch_bounds__(256) void k_finish_rows(int32_t nbrows, const int64_t* __restrict__ nc_pre,
+                                                     const int64_t* __restrict__ np_pre,
+                                                     const int64_t* __restrict__ nv_pre,
+                                                     int32_t* __restrict__ c_row_ptr, int64_t* __restrict__ prod_ptr,
+                                                     int64_t* __restrict__ c_blk_off) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i <= nbrows) c_row_ptr[i] = (int32_t)nc_pre[i];
+  if (i == 0) {
+    const int64_t nnzc = nc_pre[nbrows];
+    prod_ptr[nnzc] = np_pre[nbrows];
+    c_blk_off[nnzc] = nv_pre[nbrows];
+  }
+}
+
+hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
+                              int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_rows, dim3((nbrows + 1 + 255) / 256), dim3(256), 0, s, nbrows, nc_pre, np_pre, nv_pre,
+                     c_row_ptr, prod_ptr, c_blk_off);
+  return hipGetLastError();
+}
+
+// totals[0..3] = last entries of the four prefixes; totals[4] = flags.
+__global__ void k_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
+                                const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
+                                int64_t* totals) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    totals[0] = nc_pre[n];
+    totals[1] = np_pre[n];
+    totals[2] = nv_pre[n];
+    totals[3] = cand_pre[n];
+    totals[4] = (int64_t)*flags;
+    totals[5] = nf_pre[n];
+  }
+}
+
+hipError_t launch_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
+                                const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
+                                int64_t* totals, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_totals, dim3(1), dim3(64), 0, s, n, nc_pre, np_pre, nv_pre, cand_pre, nf_pre, flags,
+                     totals);
+  return hipGetLastError();
+}
+
+}  // namespace bsmm
