@@ -98,6 +98,7 @@ struct bsmm_matrix {
   DBuf<double> norm_a, norm_b, norm_self;
   DBuf<int64_t> rows[5], pre[5], scan_tmp, totals, fkeep, fvsz, fpos, fvoff;
   DBuf<uint32_t> flags;
+  DBuf<int32_t> work;
   int64_t* h_totals = nullptr;  // pinned, 8 entries
   // phase timing: 7 events per recorded multiply
   bool timing = false;
@@ -279,6 +280,7 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->fpos.release();
   m->fvoff.release();
   m->flags.release();
+  m->work.release();
   if (m->h_totals) (void)hipHostFree(m->h_totals);
   drop_events(m);
   delete m;
@@ -424,7 +426,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   }
   mark(C, ev, 0, s);
   // scratch
-  if (C->flags.ensure(1) != hipSuccess || C->totals.ensure(8) != hipSuccess ||
+  if (C->flags.ensure(1) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(8) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
@@ -526,7 +528,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
   const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
-  HIP_TRY(launch_numeric(na, uniform, s));
+  HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
   mark(C, ev, 5, s);
   HIP_TRY(hipMemsetAsync(out.values.p + nvals, 0, sizeof(double) * kValueSlack, s));
   mark(C, ev, 6, s);

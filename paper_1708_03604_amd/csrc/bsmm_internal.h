@@ -93,7 +93,7 @@ hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64
 hipError_t launch_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
                                 const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
                                 int64_t* totals, hipStream_t s);
-hipError_t launch_numeric(const NumArgs& a, int uniform_size, hipStream_t s);
+hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s);
 
 // filter(M, eps): keep/vsz/keep_pos/voff are scratch of nnzb (+1) entries.
 hipError_t launch_filter(const int32_t* row_ptr, const int32_t* col_idx, const int64_t* blk_off,
