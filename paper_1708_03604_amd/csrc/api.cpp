@@ -467,7 +467,15 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.row_nf = C->rows[4].p;
   g.flags = C->flags.p;
   HIP_TRY(launch_sym_count(g, s));
-  for (int x = 0; x < 5; ++x) HIP_TRY(scan_exclusive(C->rows[x].p, nbrows, C->pre[x].p, C->scan_tmp.p, s));
+  {
+    const int64_t* in[5];
+    int64_t* outp[5];
+    for (int x = 0; x < 5; ++x) {
+      in[x] = C->rows[x].p;
+      outp[x] = C->pre[x].p;
+    }
+    HIP_TRY(scan_rows(in, outp, 5, nbrows, C->scan_tmp.p, s));
+  }
   HIP_TRY(launch_gather_totals(nbrows, C->pre[0].p, C->pre[1].p, C->pre[2].p, C->pre[3].p, C->pre[4].p,
                                C->flags.p, C->totals.p, s));
   mark(C, ev, 2, s);

@@ -25,6 +25,7 @@ constexpr int kSymThreads = 256;
 constexpr int kHashSlots = 2048;   // open-addressing table over block columns
 constexpr int kMaxRowBlocks = 1024; // result blocks per C block row
 constexpr int kMaxRowA = 1024;      // stored A blocks per block row
+constexpr int kMaxRowCand = 4096;   // candidate products of a row cached in LDS
 
 // Device-side flags raised by kernels (bit mask in a uint32 word).
 enum : uint32_t {
@@ -85,6 +86,9 @@ hipError_t launch_block_norms(const int64_t* blk_off, const double* values, int3
 // tmp must hold scan_tmp_elems(n) entries; in and out must not overlap.
 int64_t scan_tmp_elems(int64_t n);
 hipError_t scan_exclusive(const int64_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+// The same for narr (<= 8) arrays at once (per-row counts).
+hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, int64_t n, int64_t* tmp,
+                     hipStream_t s);
 
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s);
 hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s);

@@ -138,6 +138,79 @@ hipError_t scan_exclusive(const int64_t* in, int64_t n, int64_t* out, int64_t* t
   return hipGetLastError();
 }
 
+// Exclusive scans of up to 8 int64 arrays of length n in one workgroup:
+// out[a][0..n] with out[a][n] = total.  Used for the per-row counts, where n
+// (block rows) is small enough that one workgroup sweeping the rows beats
+// three launches per array.
+constexpr int kRowScanThreads = 1024;
+struct ScanSet {
+  const int64_t* in[8];
+  int64_t* out[8];
+};
+
+__global__ __launch_bounds__(kRowScanThreads) void k_scan_rows(ScanSet set, int narr, int64_t n) {
+  __shared__ int64_t wsum[8][kRowScanThreads / 64];
+  __shared__ int64_t carry[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 8) carry[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += kRowScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    int64_t x[8], v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      v[a] = (a < narr && i < n) ? set.in[a][i] : 0;
+      x[a] = v[a];
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int64_t y = __shfl_up(x[a], d, 64);
+        if (lane >= d) x[a] += y;
+      }
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) wsum[a][wave] = x[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      if (a >= narr) continue;
+      int64_t off = carry[a];
+      for (int w = 0; w < wave; ++w) off += wsum[a][w];
+      if (i < n) set.out[a][i] = off + x[a] - v[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < narr) {
+      int64_t tot = 0;
+      for (int w = 0; w < kRowScanThreads / 64; ++w) tot += wsum[threadIdx.x][w];
+      carry[threadIdx.x] += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < narr) set.out[threadIdx.x][n] = carry[threadIdx.x];
+}
+
+hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, int64_t n, int64_t* tmp,
+                     hipStream_t s) {
+  if (n > (1 << 16)) {
+    for (int a = 0; a < narr; ++a) {
+      hipError_t e = scan_exclusive(in[a], n, out[a], tmp, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  ScanSet set{};
+  for (int a = 0; a < narr; ++a) {
+    set.in[a] = in[a];
+    set.out[a] = out[a];
+  }
+  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kRowScanThreads), 0, s, set, narr, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- filter
 
 // keep[b] = 1 if eps <= 0 or norm > eps; vsz[b] = its value count if kept.

@@ -268,9 +268,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
   for (int x = 0; x < 36; ++x) acc[x] = 0.0;
 
   // Finish every C block that ends at p (blocks without products included):
-  // sum the four K slices, apply alpha/beta, store.  Returns false when the
-  // wave has no products left.
-  auto advance = [&]() -> bool {
+  // sum the four K slices, apply alpha, park the block row-major in the LDS
+  // stage that is free (`freestage`), then add beta*C_in and store it with
+  // contiguous, coalesced accesses.  Returns false when the wave has no
+  // products left.
+  auto advance = [&](auto freestage) -> bool {
+    constexpr int fs = decltype(freestage)::value;
+    double* const tile = &lds[wv][fs][0];
     while (p == pe) {
 #pragma unroll
       for (int x = 0; x < 18; ++x) {
@@ -283,27 +287,35 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
         acc[x] = acc[x] + acc[x + 9];
       }
       // this lane's outputs are tile slots y = 9*s + x
-      int idx[9];
 #pragma unroll
       for (int x = 0; x < 9; ++x) {
         const int y = 9 * s + x;
         const int R = 6 * rho + y / 6, Cc = 6 * gam + y % 6;
-        idx[x] = (R < S && Cc < S) ? R * S + Cc : -1;
-        acc[x] = alpha * acc[x];
+        if (R < S && Cc < S) tile[R * S + Cc] = alpha * acc[x];
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int32_t o = use_old ? c_old_idx[c] : -1;
+      double* out = Cv + (int64_t)c * NE + lane;
+      const double* tl = tile + lane;
       if (o >= 0) {
-        const double* ov = Ov + (int64_t)o * NE;
-        double ol[9];
+        const double* ov = Ov + (int64_t)o * NE + lane;
+        double ol[PER];
 #pragma unroll
-        for (int x = 0; x < 9; ++x) ol[x] = ov[idx[x] < 0 ? 0 : idx[x]];
+        for (int u = 0; u < PER - 1; ++u) ol[u] = ov[64 * u];
+        ol[PER - 1] = tail ? ov[64 * (PER - 1)] : 0.0;
 #pragma unroll
-        for (int x = 0; x < 9; ++x) acc[x] = acc[x] + beta * ol[x];
+        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u] + beta * ol[u];
+        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)] + beta * ol[PER - 1];
+      } else {
+#pragma unroll
+        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u];
+        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)];
       }
-      double* out = Cv + (int64_t)c * NE;
-#pragma unroll
-      for (int x = 0; x < 9; ++x)
-        if (idx[x] >= 0) out[idx[x]] = acc[x];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int x = 0; x < 36; ++x) acc[x] = 0.0;
       ++c;
@@ -319,12 +331,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
     return true;
   };
 
-  // products alternate between LDS stage 0 and stage 1
+  // products alternate between LDS stage 0 and stage 1; a block that ends
+  // after a stage-s product is finished in stage s, which is free by then
   for (;;) {
-    if (p == pe && !advance()) break;
+    if (p == pe && !advance(std::integral_constant<int, 1>())) break;
     step(std::integral_constant<int, 0>());
     ++p;
-    if (p == pe && !advance()) break;
+    if (p == pe && !advance(std::integral_constant<int, 0>())) break;
     step(std::integral_constant<int, 1>());
     ++p;
   }

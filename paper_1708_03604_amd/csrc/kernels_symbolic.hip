@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
   __shared__ int32_t spre[kMaxRowBlocks];
   __shared__ int32_t cursor[kMaxRowBlocks];
   __shared__ int64_t svoff[kMaxRowBlocks];
+  __shared__ int32_t cand_j[kMaxRowCand];  // column of each kept candidate, -1 if filtered
   __shared__ int32_t s_ne;
   const int tid = threadIdx.x;
   constexpr int kPer = kMaxRowBlocks / kSymThreads;
@@ -255,12 +256,18 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     int32_t a0, nA;
     const int32_t T = load_row(g, i, ra, &a0, &nA);
     if (T < 0) continue;  // uniform over the workgroup; reported by the count pass
+    const bool cached = T <= kMaxRowCand;
     for (int32_t t = tid; t < T; t += kSymThreads) {
       int32_t p, q;
       candidate(ra, nA, t, &p, &q);
-      if (!keep_product(g, ra, p, q)) continue;
+      if (!keep_product(g, ra, p, q)) {
+        if (cached) cand_j[t] = -1;
+        continue;
+      }
+      const int32_t j = g.B.col_idx[q];
+      if (cached) cand_j[t] = j;
       bool fresh;
-      const int h = hash_insert(hkey, g.B.col_idx[q], &fresh);
+      const int h = hash_insert(hkey, j, &fresh);
       if (h >= 0) atomicAdd(&hcnt[h], 1);
     }
     if (g.use_old) {
@@ -335,8 +342,29 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
       }
     }
     __syncthreads();
-    // Place the kept products; order inside a C block is fixed up below.
     const int64_t prow = g.row_pstart[i];
+    if (cached) {
+      // Place the kept products in A order (= ascending k): the candidates of
+      // one A entry have distinct columns, so they never share a C block and
+      // one pass per A entry needs no atomics.
+      for (int32_t p = 0; p < nA; ++p) {
+        const int32_t t0 = ra.pre[p], len = ra.pre[p + 1] - t0;
+        for (int32_t u = tid; u < len; u += kSymThreads) {
+          const int32_t j = cand_j[t0 + u];
+          if (j >= 0) {
+            const int r = hrank[hash_find(hkey, j)];
+            const int32_t pos = spre[r] + cursor[r];
+            cursor[r] = cursor[r] + 1;
+            g.prod_a[prow + pos] = a0 + p;
+            g.prod_b[prow + pos] = ra.qs[p] + u;
+          }
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+    // Rows with more candidates than the LDS cache: place with atomics, then
+    // sort each C block's products by A block index (= by inner index k).
     for (int32_t t = tid; t < T; t += kSymThreads) {
       int32_t p, q;
       candidate(ra, nA, t, &p, &q);
@@ -348,7 +376,6 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
       g.prod_b[prow + pos] = q;
     }
     __syncthreads();
-    // Sort each C block's products by A block index (= by inner index k).
     for (int r = tid; r < nC; r += kSymThreads) {
       int32_t* pa = g.prod_a + prow + spre[r];
       int32_t* pb = g.prod_b + prow + spre[r];
