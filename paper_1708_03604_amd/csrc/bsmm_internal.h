@@ -25,7 +25,6 @@ constexpr int kSymThreads = 256;
 constexpr int kHashSlots = 2048;   // open-addressing table over block columns
 constexpr int kMaxRowBlocks = 1024; // result blocks per C block row
 constexpr int kMaxRowA = 1024;      // stored A blocks per block row
-constexpr int kMaxRowCand = 4096;   // candidate products of a row cached in LDS
 
 // Device-side flags raised by kernels (bit mask in a uint32 word).
 enum : uint32_t {

@@ -230,18 +230,88 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
 
 // ------------------------------------------------------------------ fill
 
+// Row state of the fill pass (the count pass also needs the inner sizes).
+struct RowFill {
+  int32_t qs[kMaxRowA];        // first B block of B row k_p
+  int32_t pre[kMaxRowA + 1];   // exclusive prefix of B row lengths
+  double nrm[kMaxRowA];        // norm of A(i, k_p)
+};
+
+// The row's candidates, in chunks of kCandCache, hold the hash slot of their
+// block column (or -1 when the filter drops them).
+constexpr int kCandCache = 8192;
+static_assert(kHashSlots <= 32767, "slots must fit in int16");
+
+__device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill& ra, int32_t* a0_out, int32_t* na_out) {
+  const int tid = threadIdx.x;
+  const int32_t a0 = g.A.row_ptr[i];
+  const int32_t nA = g.A.row_ptr[i + 1] - a0;
+  *a0_out = a0;
+  *na_out = nA;
+  if (nA > kMaxRowA) return -1;
+  constexpr int kPer = kMaxRowA / kSymThreads;
+  int32_t len[kPer];
+  int64_t mysum = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int32_t p = tid * kPer + u;
+    len[u] = 0;
+    if (p < nA) {
+      const int32_t k = g.A.col_idx[a0 + p];
+      const int32_t qs = g.B.row_ptr[k];
+      len[u] = g.B.row_ptr[k + 1] - qs;
+      ra.qs[p] = qs;
+      ra.nrm[p] = g.use_eps ? g.normA[a0 + p] : 0.0;
+    }
+    mysum += len[u];
+  }
+  int64_t total;
+  int64_t run = sym_scan(mysum, &total);
+  if (total > 0x7fffffffLL) return -1;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int32_t p = tid * kPer + u;
+    if (p < nA) ra.pre[p] = (int32_t)run;
+    run += len[u];
+  }
+  if (tid == 0) ra.pre[nA] = (int32_t)total;
+  __syncthreads();
+  return (int32_t)total;
+}
+
+__device__ __forceinline__ int32_t fill_entry_of(const RowFill& ra, int32_t nA, int32_t t) {
+  int lo = 0, hi = nA - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ra.pre[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool fill_keep(const SymArgs& g, const RowFill& ra, int32_t p, int32_t q) {
+  if (!g.use_eps) return true;
+  const double prod = ra.nrm[p] * g.normB[q];
+  return prod > g.eps;
+}
+
+// One workgroup per C block row.  After the hash has merged the kept
+// candidates by column, the columns are ranked (sorted pattern), the counts
+// scanned (each C block's slice of the stack), and the products placed in
+// ascending A entry order, i.e. ascending k: in one pass per A entry p the
+// candidates of p have distinct columns, so each C block receives at most one
+// product per pass and a plain LDS cursor per block suffices.
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
   __shared__ int32_t hkey[kHashSlots];
-  __shared__ int32_t hcnt[kHashSlots];
+  __shared__ int32_t hcnt[kHashSlots];  // product count per slot, then the slot's rank
   __shared__ int32_t hold[kHashSlots];
-  __shared__ int32_t hrank[kHashSlots];
-  __shared__ RowA ra;
+  __shared__ RowFill ra;
   __shared__ int32_t ekey[kMaxRowBlocks];
   __shared__ int32_t eslot[kMaxRowBlocks];
   __shared__ int32_t spre[kMaxRowBlocks];
   __shared__ int32_t cursor[kMaxRowBlocks];
-  __shared__ int64_t svoff[kMaxRowBlocks];
-  __shared__ int32_t cand_j[kMaxRowCand];  // column of each kept candidate, -1 if filtered
+  __shared__ int32_t svs[kMaxRowBlocks];
+  __shared__ int16_t cslot[kCandCache];
   __shared__ int32_t s_ne;
   const int tid = threadIdx.x;
   constexpr int kPer = kMaxRowBlocks / kSymThreads;
@@ -254,21 +324,19 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     if (tid == 0) s_ne = 0;
     __syncthreads();
     int32_t a0, nA;
-    const int32_t T = load_row(g, i, ra, &a0, &nA);
+    const int32_t T = load_row_fill(g, i, ra, &a0, &nA);
     if (T < 0) continue;  // uniform over the workgroup; reported by the count pass
-    const bool cached = T <= kMaxRowCand;
+    const bool one_chunk = T <= kCandCache;
     for (int32_t t = tid; t < T; t += kSymThreads) {
-      int32_t p, q;
-      candidate(ra, nA, t, &p, &q);
-      if (!keep_product(g, ra, p, q)) {
-        if (cached) cand_j[t] = -1;
-        continue;
+      const int32_t p = fill_entry_of(ra, nA, t);
+      const int32_t q = ra.qs[p] + (t - ra.pre[p]);
+      int h = -1;
+      if (fill_keep(g, ra, p, q)) {
+        bool fresh;
+        h = hash_insert(hkey, g.B.col_idx[q], &fresh);
+        if (h >= 0) atomicAdd(&hcnt[h], 1);
       }
-      const int32_t j = g.B.col_idx[q];
-      if (cached) cand_j[t] = j;
-      bool fresh;
-      const int h = hash_insert(hkey, j, &fresh);
-      if (h >= 0) atomicAdd(&hcnt[h], 1);
+      if (one_chunk) cslot[t] = (int16_t)h;
     }
     if (g.use_old) {
       const int32_t o1 = g.Cin.row_ptr[i + 1];
@@ -291,34 +359,31 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     __syncthreads();
     const int32_t nC = s_ne;
     if (nC > kMaxRowBlocks) continue;  // reported by the count pass
-    // Rank the distinct columns: rank = number of smaller columns.
+    // Rank the distinct columns (rank = number of smaller columns), move the
+    // counts into rank order and leave each slot's rank in hcnt.
+    const int32_t crow = g.c_row_ptr[i];
     for (int e = tid; e < nC; e += kSymThreads) {
       const int32_t key = ekey[e];
       int r = 0;
       for (int e2 = 0; e2 < nC; ++e2) r += (ekey[e2] < key) ? 1 : 0;
-      hrank[eslot[e]] = r;
-    }
-    __syncthreads();
-    const int32_t crow = g.c_row_ptr[i];
-    for (int e = tid; e < nC; e += kSymThreads) {
       const int h = eslot[e];
-      const int r = hrank[h];
       spre[r] = hcnt[h];
-      svoff[r] = g.c_col_sizes[ekey[e]];
-      g.c_col_idx[crow + r] = ekey[e];
+      hcnt[h] = r;
+      svs[r] = g.c_col_sizes[key];
+      g.c_col_idx[crow + r] = key;
       g.c_old_idx[crow + r] = hold[h];
     }
     __syncthreads();
     // Scan the per-column product counts and value sizes in rank order.
     {
       int32_t cnt[kPer];
-      int64_t vs[kPer];
+      int32_t vs[kPer];
       int64_t sc = 0, sv = 0;
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const int r = tid * kPer + u;
         cnt[u] = r < nC ? spre[r] : 0;
-        vs[u] = r < nC ? svoff[r] : 0;
+        vs[u] = r < nC ? svs[r] : 0;
         sc += cnt[u];
         sv += vs[u];
       }
@@ -343,56 +408,32 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     }
     __syncthreads();
     const int64_t prow = g.row_pstart[i];
-    if (cached) {
-      // Place the kept products in A order (= ascending k): the candidates of
-      // one A entry have distinct columns, so they never share a C block and
-      // one pass per A entry needs no atomics.
-      for (int32_t p = 0; p < nA; ++p) {
-        const int32_t t0 = ra.pre[p], len = ra.pre[p + 1] - t0;
-        for (int32_t u = tid; u < len; u += kSymThreads) {
-          const int32_t j = cand_j[t0 + u];
-          if (j >= 0) {
-            const int r = hrank[hash_find(hkey, j)];
+    for (int32_t t0 = 0; t0 < T; t0 += kCandCache) {
+      const int32_t t1 = T - t0 > kCandCache ? t0 + kCandCache : T;
+      if (!one_chunk) {
+        for (int32_t t = t0 + tid; t < t1; t += kSymThreads) {
+          const int32_t p = fill_entry_of(ra, nA, t);
+          const int32_t q = ra.qs[p] + (t - ra.pre[p]);
+          cslot[t - t0] = (int16_t)(fill_keep(g, ra, p, q) ? hash_find(hkey, g.B.col_idx[q]) : -1);
+        }
+        __syncthreads();
+      }
+      for (int32_t p = fill_entry_of(ra, nA, t0); p < nA && ra.pre[p] < t1; ++p) {
+        const int32_t u0 = ra.pre[p] > t0 ? ra.pre[p] : t0;
+        const int32_t u1 = ra.pre[p + 1] < t1 ? ra.pre[p + 1] : t1;
+        for (int32_t t = u0 + tid; t < u1; t += kSymThreads) {
+          const int h = cslot[t - t0];
+          if (h >= 0) {
+            const int r = hcnt[h];
             const int32_t pos = spre[r] + cursor[r];
             cursor[r] = cursor[r] + 1;
             g.prod_a[prow + pos] = a0 + p;
-            g.prod_b[prow + pos] = ra.qs[p] + u;
+            g.prod_b[prow + pos] = ra.qs[p] + (t - ra.pre[p]);
           }
         }
         __syncthreads();
       }
-      continue;
     }
-    // Rows with more candidates than the LDS cache: place with atomics, then
-    // sort each C block's products by A block index (= by inner index k).
-    for (int32_t t = tid; t < T; t += kSymThreads) {
-      int32_t p, q;
-      candidate(ra, nA, t, &p, &q);
-      if (!keep_product(g, ra, p, q)) continue;
-      const int h = hash_find(hkey, g.B.col_idx[q]);
-      const int r = hrank[h];
-      const int32_t pos = spre[r] + atomicAdd(&cursor[r], 1);
-      g.prod_a[prow + pos] = a0 + p;
-      g.prod_b[prow + pos] = q;
-    }
-    __syncthreads();
-    for (int r = tid; r < nC; r += kSymThreads) {
-      int32_t* pa = g.prod_a + prow + spre[r];
-      int32_t* pb = g.prod_b + prow + spre[r];
-      const int n = cursor[r];
-      for (int x = 1; x < n; ++x) {
-        const int32_t ka = pa[x], kb = pb[x];
-        int y = x - 1;
-        while (y >= 0 && pa[y] > ka) {
-          pa[y + 1] = pa[y];
-          pb[y + 1] = pb[y];
-          --y;
-        }
-        pa[y + 1] = ka;
-        pb[y + 1] = kb;
-      }
-    }
-    __syncthreads();
   }
 }
 
