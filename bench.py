@@ -10,6 +10,7 @@ JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -115,6 +116,74 @@ def cpu_baseline(w, gpu_flops_per_step, target_s=12.0):
             "seconds": dt}
 
 
+def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_ms):
+    """Same multiply with the operands split into three BF16 terms on matrix
+    cores; error against the FP64 result (which matches the oracle within
+    1e-12, see the parity tests)."""
+    from paper_1708_03604_amd import bsmm
+    import torch
+    _, _, ref = dC.to_host()
+    dS = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
+
+    def step():
+        bsmm.multiply(w.alpha, dA, dB, w.beta, dCin, dS, w.eps, prec=bsmm.BSMM_SPLIT_BF16X3, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    bsmm.bsmm_timing(dS.handle, 1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    phases, nrec = bsmm.bsmm_phase_times(dS.handle)
+    bsmm.bsmm_timing(dS.handle, 0)
+    stats = bsmm.bsmm_stats(dS.handle)
+    _, _, got = dS.to_host()
+    dS.close()
+    err = got - ref
+    rel = float(np.linalg.norm(err) / np.linalg.norm(ref))
+    numeric = phases["numeric"] / max(nrec, 1)
+    return {"value": round(stats["useful_flops"] / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+            "ms_per_step": round(ms, 4), "numeric_ms": round(numeric, 4),
+            "speedup_vs_fp64": round(fp64_ms / ms, 3), "numeric_speedup_vs_fp64": round(fp64_numeric_ms / numeric, 3),
+            "rel_frobenius_vs_fp64": rel, "max_abs_err": float(np.max(np.abs(err))),
+            "max_abs_err_over_max_abs_c": float(np.max(np.abs(err)) / np.max(np.abs(ref))),
+            "stated_bound": "per element 2^-15 |alpha| (|A||B|)_ij + FP64 rounding",
+            "note": "numeric_ms includes splitting A and B into BF16 terms"}
+
+
+def chain_leg(nmol, steps=12, eps=1e-7, replays=3):
+    """Newton-Schulz sign chain (12 steps, filter 1e-7) on a symmetric,
+    Gershgorin-scaled molecule matrix, captured in one HIP graph; returns the
+    graph replay throughput and the FP64 residual."""
+    import torch
+    from paper_1708_03604_amd import workloads as W
+    from paper_1708_03604_amd.chain import SignChain
+    X0, info = W.symmetric_scaled(nmol=nmol)
+    ch = SignChain(X0, steps=steps, eps=eps)
+    flops, prods, blocks = ch.count_flops()
+    ch.capture()
+    ch.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        ch.replay()
+    ch.stream.synchronize()
+    dt = (time.perf_counter() - t0) / replays
+    res = float(ch.residual.cpu()[0])
+    n = int(info["N"])
+    out = {"workload": f"sign chain: {nmol} molecules as 23x23 blocks (N={n}), {steps} Newton-Schulz steps, "
+                       f"filter_eps={eps}, {ch.multiplies()} multiplies + {2 * steps} filters + residual, "
+                       f"one HIP graph",
+           "value": round(flops / dt / 1e9, 2), "unit": "GFLOP/s", "ms_per_chain": round(dt * 1e3, 3),
+           "useful_gflop_per_chain": round(flops / 1e9, 3), "products_per_chain": int(prods),
+           "x_blocks_per_step": blocks, "residual_fro": res,
+           "residual_rel": res / math.sqrt(n), "replays": replays}
+    ch.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="molecules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chain-nmol", type=int, default=256,
+                    help="molecules of the sign-chain leg (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device to device three times (calibrates the HBM traffic counters)")
     args = ap.parse_args()
@@ -205,6 +276,18 @@ def main():
         "whole_step_frac_of_fp64_peak": round(value / 1e3 / FP64_PEAK_TFLOPS, 4),
         "phases_ms": {k: round(v, 4) for k, v in phase_avg.items()},
     }
+    if args.workload == "molecules":
+        log("[bench] split precision (three BF16 terms on matrix cores)")
+        out["split_bf16x3"] = split_leg(w, dA, dB, dCin, dC, stream, args.steps, args.warmup, ms_per_step,
+                                        numeric_ms)
+        sp = out["split_bf16x3"]
+        log(f"[bench] split: {sp['ms_per_step']} ms/step ({sp['speedup_vs_fp64']}x), rel Frobenius error "
+            f"{sp['rel_frobenius_vs_fp64']:.2e}")
+    if args.chain_nmol > 0 and args.workload == "molecules":
+        log(f"[bench] sign chain on {args.chain_nmol} molecules")
+        out["chain"] = chain_leg(args.chain_nmol)
+        log(f"[bench] chain: {out['chain']['ms_per_chain']} ms, {out['chain']['value']} GFLOP/s, "
+            f"residual {out['chain']['residual_fro']:.3e}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, flops)

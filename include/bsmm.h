@@ -32,6 +32,7 @@ extern "C" {
 #endif
 
 typedef struct bsmm_matrix* bsmm_mat;
+typedef struct bsmm_graph_s* bsmm_graph;
 
 typedef enum {
   BSMM_OK = 0,
@@ -46,9 +47,17 @@ typedef enum {
   BSMM_E_UNSUPPORTED = 8   /* valid input outside what this build handles (message says why) */
 } bsmm_status;
 
-/* Arithmetic of the block products. */
+/* Arithmetic of the block products.  Norms, filter decisions, the symbolic
+ * phase and the C accumulation are FP64 in every mode. */
 typedef enum {
-  BSMM_FP64 = 0 /* FP64 products and accumulation */
+  BSMM_FP64 = 0,          /* FP64 products and accumulation */
+  BSMM_SPLIT_F32X2 = 1,   /* two FP32 terms per value: not built (BSMM_E_UNSUPPORTED) */
+  BSMM_SPLIT_BF16X3 = 2   /* three BF16 terms per value, the six term products of combined
+                             order <= 2 on BF16 matrix cores with FP32 accumulation, each
+                             block product added in FP64; 23x23 blocks only
+                             (BSMM_E_UNSUPPORTED otherwise).  Per C element the error is
+                             below 2^-15 * |alpha| * sum_k |A(i,k)| |B(k,j)| plus FP64
+                             rounding. */
 } bsmm_prec;
 
 enum { BSMM_PTR_HOST = 0, BSMM_PTR_DEVICE = 1 };
@@ -95,35 +104,45 @@ bsmm_status bsmm_destroy(bsmm_mat m);
  *     (and C_in when read) must have A's row sizes and B's column sizes
  *     (BSMM_E_SHAPE).
  *   - alpha, beta and filter_eps must be finite (BSMM_E_ARG).
- *   - Synchronises `stream` once, after the symbolic phase, to size C_out.
+ *   - Synchronises `stream` once, after the symbolic phase, to size C_out,
+ *     unless C_out is reserved (bsmm_reserve): then it never synchronises.
  * On error C_out is left as it was.
  */
 bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in,
                           bsmm_mat C_out, double filter_eps, int prec, void* stream);
+/* (prec is a bsmm_prec; an unknown value is BSMM_E_ARG.) */
 
 /*
  * Drop every block whose Frobenius norm is not above eps (eps <= 0 keeps
  * all blocks); compacts the pattern and values in place (Section 2: the
- * filter "increases sparsity").  Synchronises `stream` to read the new size.
+ * filter increases sparsity).  Synchronises `stream` to read the new size,
+ * except for a reserved matrix (see bsmm_reserve), where it stays on the
+ * device.
  */
 bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream);
 
 /*
  * Frobenius norm of every stored block, in CSR order, into out[nnzb]
- * (device memory owned by the caller).  The sum of squares runs in a fixed
+ * (device memory owned by the caller; for a device-sized matrix it must hold
+ * the reserved block capacity).  The sum of squares runs in a fixed
  * order (64 interleaved partial sums with fused multiply-add, then a pairwise
  * tree, then a correctly rounded square root), so the values are bitwise
  * reproducible.
  */
 bsmm_status bsmm_norms(bsmm_mat m, double* out, void* stream);
 
-/* Sizes of a matrix (any pointer may be NULL).  Host-side metadata, no sync. */
+/* Sizes of a matrix (any pointer may be NULL).  Host-side metadata; if the
+ * matrix was last written by a reserved (device-sized) multiply or filter,
+ * this first waits for the device and reads the sizes back, and reports a
+ * reserved operation that overflowed (BSMM_E_CAPACITY; the matrix is then
+ * empty). */
 bsmm_status bsmm_info(bsmm_mat m, int32_t* nbrows, int32_t* nbcols, int32_t* nnzb, int64_t* nvals);
 
 /*
  * Copy the pattern and values out: row_ptr[nbrows+1], col_idx[nnzb],
  * values[nvals] (any pointer may be NULL), host or device memory per
- * ptr_kind.  Synchronises `stream`.
+ * ptr_kind.  Synchronises `stream` (and reads device-resident sizes back,
+ * see bsmm_info).
  */
 bsmm_status bsmm_export(bsmm_mat m, int32_t* row_ptr, int32_t* col_idx, double* values, int ptr_kind,
                         void* stream);
@@ -137,8 +156,50 @@ bsmm_status bsmm_export(bsmm_mat m, int32_t* row_ptr, int32_t* col_idx, double* 
 bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t* st_b, int64_t* nprod,
                               int ptr_kind, void* stream);
 
-/* Counters of the last multiply that wrote C (zeros if none). */
+/* Counters of the last multiply that wrote C (zeros if none).  Waits for the
+ * device like bsmm_info when C is device-sized. */
 bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
+
+/*
+ * Graph-capturable mode.  Reserve device capacity in m for the results of the
+ * multiplies and filters that will write it: at most max_nnzb blocks,
+ * max_nvals values and max_products block products per multiply.  From then
+ * on, bsmm_multiply(..., C = m, ...) and bsmm_filter(m, ...) neither allocate
+ * nor synchronise: the result sizes stay on the device, kernels read them
+ * there, and the host learns them at the next synchronising call (info,
+ * export, export_stack, stats).  A result that does not fit is not written;
+ * the overflow is recorded on the device and reported by that call as
+ * BSMM_E_CAPACITY (or BSMM_E_UNSUPPORTED for a row beyond the symbolic
+ * limits), after which m is empty.  The current contents of m are kept.
+ * Inputs of such a multiply must not hold more blocks than the capacity of
+ * the output (the norm scratch of the filter is sized by it).  Synchronises
+ * `stream` once.  Capacities must be >= 1 and block/product capacities below
+ * 2^31.
+ */
+bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_t max_products, void* stream);
+
+/*
+ * ||m||_F of all stored values into out[0] (device memory owned by the
+ * caller), in FP64 with a fixed summation order (256 contiguous slices, each
+ * summed by 256 interleaved fused multiply-add partials and a pairwise tree;
+ * the slice sums by a pairwise tree; a correctly rounded square root).
+ * Asynchronous; works on device-sized matrices (the Newton-Schulz residual).
+ */
+bsmm_status bsmm_frobenius(bsmm_mat m, double* out, void* stream);
+
+/*
+ * HIP graph capture of a sequence of calls on one created (non-default)
+ * stream: bsmm_capture_begin, then reserved multiplies / filters /
+ * frobenius on that stream, then bsmm_capture_end, which instantiates the
+ * graph.  bsmm_graph_launch replays it on any stream; each replay re-runs the
+ * captured calls on the same buffers.  Calls that would allocate or
+ * synchronise must not be captured (they fail the capture); run the sequence
+ * once before capturing so every scratch buffer has its final size.
+ */
+bsmm_status bsmm_capture_begin(void* stream);
+bsmm_status bsmm_capture_end(void* stream, bsmm_graph* out);
+bsmm_status bsmm_graph_launch(bsmm_graph g, void* stream);
+bsmm_status bsmm_graph_destroy(bsmm_graph g);
 
 /* Phases timed by bsmm_timing / bsmm_phase_times. */
 enum {

@@ -19,6 +19,8 @@ BSMM_OK = 0
 STATUS_NAMES = {0: "BSMM_OK", 1: "BSMM_E_ARG", 2: "BSMM_E_SHAPE", 3: "BSMM_E_PATTERN", 4: "BSMM_E_ALIAS",
                 5: "BSMM_E_NOMEM", 6: "BSMM_E_CAPACITY", 7: "BSMM_E_HIP", 8: "BSMM_E_UNSUPPORTED"}
 BSMM_FP64 = 0
+BSMM_SPLIT_F32X2 = 1
+BSMM_SPLIT_BF16X3 = 2
 BSMM_PTR_HOST = 0
 BSMM_PTR_DEVICE = 1
 
@@ -50,6 +52,12 @@ SIGNATURES = {
     "bsmm_timing": ([_vp, _int], _int),
     "bsmm_phase_times": ([_vp, _vp, _vp], _int),
     "bsmm_last_error": ([], ctypes.c_char_p),
+    "bsmm_reserve": ([_vp, _i64, _i64, _i64, _vp], _int),
+    "bsmm_frobenius": ([_vp, _vp, _vp], _int),
+    "bsmm_capture_begin": ([_vp], _int),
+    "bsmm_capture_end": ([_vp, _vp], _int),
+    "bsmm_graph_launch": ([_vp, _vp], _int),
+    "bsmm_graph_destroy": ([_vp], _int),
 }
 
 _lib = None
@@ -188,6 +196,34 @@ def bsmm_phase_times(C):
 
 def bsmm_last_error():
     return lib().bsmm_last_error().decode()
+
+
+def bsmm_reserve(M, max_nnzb, max_nvals, max_products, stream=None):
+    _check("bsmm_reserve", lib().bsmm_reserve(M, int(max_nnzb), int(max_nvals), int(max_products),
+                                              _stream(stream)))
+
+
+def bsmm_frobenius(M, out, stream=None):
+    p, _ = _addr(out)
+    _check("bsmm_frobenius", lib().bsmm_frobenius(M, p, _stream(stream)))
+
+
+def bsmm_capture_begin(stream):
+    _check("bsmm_capture_begin", lib().bsmm_capture_begin(_stream(stream)))
+
+
+def bsmm_capture_end(stream):
+    g = ctypes.c_void_p()
+    _check("bsmm_capture_end", lib().bsmm_capture_end(_stream(stream), ctypes.byref(g)))
+    return g
+
+
+def bsmm_graph_launch(g, stream=None):
+    _check("bsmm_graph_launch", lib().bsmm_graph_launch(g, _stream(stream)))
+
+
+def bsmm_graph_destroy(g):
+    _check("bsmm_graph_destroy", lib().bsmm_graph_destroy(g))
 
 
 # ------------------------------------------------------------ convenience

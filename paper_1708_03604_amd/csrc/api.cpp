@@ -76,7 +76,8 @@ struct Storage {
   }
 };
 
-constexpr int64_t kValueSlack = 64;
+constexpr int64_t kValueSlack = kValueSlackDoubles;
+constexpr int kPinned = 16;
 
 }  // namespace
 
@@ -87,6 +88,7 @@ struct bsmm_matrix {
   int32_t nnzb = 0;
   int64_t nvals = 0;
   int uniform = 0;  // common block edge if every row and column size is equal, else 0
+  int max_edge = 0; // largest row or column block size
   Storage cur, spare;
   // product stack of the last multiply that wrote this matrix
   DBuf<int64_t> prod_ptr;
@@ -94,12 +96,25 @@ struct bsmm_matrix {
   int64_t nprod = 0;
   bool has_stack = false;
   bsmm_mult_stats stats{};
+  // Size record on the device: {nnzb, nvals, error bits, 0}, kept current by
+  // every operation that writes the matrix.  A reserved matrix is written
+  // without host synchronisation (possibly by graph replays the host does not
+  // see), so its host-side sizes and counters are re-read from the device at
+  // every synchronising call.
+  DBuf<int64_t> dsz;
+  int64_t cap_nnzb = 0, cap_nvals = 0, cap_nprod = 0;  // reserved capacity (0: not reserved)
+  DBuf<double> frob_tmp;
   // scratch
   DBuf<double> norm_a, norm_b, norm_self;
   DBuf<int64_t> rows[5], pre[5], scan_tmp, totals, fkeep, fvsz, fpos, fvoff;
   DBuf<uint32_t> flags;
   DBuf<int32_t> work;
-  int64_t* h_totals = nullptr;  // pinned, 8 entries
+  DBuf<int4> class_list;          // C blocks by padded shape class (small-block path), 2 per block
+  DBuf<int4> prod_desc;           // per product operand offsets (small-block path)
+  DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
+  DBuf<int64_t> class_cnt, class_pre;
+  DBuf<int32_t> class_start;
+  int64_t* h_totals = nullptr;  // pinned, kPinned entries
   // phase timing: 7 events per recorded multiply
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -149,7 +164,7 @@ hipError_t ensure_storage(Storage& st, int32_t nbrows, int64_t nnzb, int64_t nva
 
 bsmm_status ensure_pinned(bsmm_matrix* m) {
   if (!m->h_totals) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&m->h_totals), 8 * sizeof(int64_t), 0) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&m->h_totals), kPinned * sizeof(int64_t), 0) != hipSuccess) {
       m->h_totals = nullptr;
       return fail(BSMM_E_NOMEM, "pinned host allocation failed");
     }
@@ -171,6 +186,53 @@ hipEvent_t* mark(bsmm_matrix* m, size_t base, int k, hipStream_t s) {
   if (!m->timing) return nullptr;
   (void)hipEventRecord(m->events[base + k], s);
   return &m->events[base + k];
+}
+
+// Upper bound on the stored blocks / values (exact unless device-sized).
+int64_t blocks_bound(const bsmm_matrix* m) { return m->cap_nnzb > 0 ? m->cap_nnzb : m->nnzb; }
+
+// Bring the host copy of a device-sized matrix's sizes (and of the counters of
+// its last multiply) up to date; synchronises `s`.  A reserved operation that
+// overflowed leaves the matrix empty and is reported here.
+bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
+  if (m->cap_nnzb == 0) return BSMM_OK;
+  bsmm_status st = ensure_pinned(m);
+  if (st != BSMM_OK) return st;
+  // the record may have been written on any stream: with no stream given,
+  // wait for the whole device
+  if (!s) HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpyAsync(m->h_totals, m->dsz.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(m->h_totals + 4, m->totals.p, kTotCount * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t err = m->h_totals[2];
+  if (err) {
+    m->nnzb = 0;
+    m->nvals = 0;
+    m->nprod = 0;
+    m->has_stack = false;
+    m->stats = bsmm_mult_stats{};
+    const int64_t zero[3] = {0, 0, 0};
+    HIP_TRY(hipMemsetAsync(m->cur.row_ptr.p, 0, sizeof(int32_t) * (m->nbrows + 1), s));
+    HIP_TRY(hipMemsetAsync(m->cur.blk_off.p, 0, sizeof(int64_t), s));
+    HIP_TRY(hipMemcpyAsync(m->dsz.p, zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(m->totals.p, 0, kTotCount * sizeof(int64_t), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err & (kFlagRowTooManyA | kFlagRowTooManyC))
+      return fail(BSMM_E_UNSUPPORTED, "a reserved multiply met a block row beyond the symbolic pass limits "
+                                      "(A rows <= " + std::to_string(kMaxRowA) + ", C rows <= " +
+                                      std::to_string(kMaxRowBlocks) + " blocks); the matrix was emptied");
+    return fail(BSMM_E_CAPACITY, "a reserved multiply exceeded the reserved capacity; the matrix was emptied");
+  }
+  m->nnzb = (int32_t)m->h_totals[0];
+  m->nvals = m->h_totals[1];
+  const int64_t* t = m->h_totals + 4;
+  m->nprod = t[kTotNprod];
+  m->stats.candidates = t[kTotCand];
+  m->stats.products = t[kTotNprod];
+  m->stats.nnzb = t[kTotNnzc];
+  m->stats.nvals = t[kTotNvals];
+  m->stats.useful_flops = 2.0 * (double)t[kTotFlopHalf];
+  return BSMM_OK;
 }
 
 }  // namespace
@@ -222,6 +284,8 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
   for (int32_t j = 0; j < nbcols && u; ++j)
     if (col_sizes[j] != u) u = 0;
   m->uniform = u;
+  for (int32_t i = 0; i < nbrows; ++i) m->max_edge = std::max(m->max_edge, row_sizes[i]);
+  for (int32_t j = 0; j < nbcols; ++j) m->max_edge = std::max(m->max_edge, col_sizes[j]);
   m->nnzb = nnzb;
   m->nvals = nvals;
   auto cleanup = [&](bsmm_status code, const std::string& msg) {
@@ -230,8 +294,10 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
   };
   if (m->d_row_sizes.ensure(std::max(nbrows, 1)) != hipSuccess ||
       m->d_col_sizes.ensure(std::max(nbcols, 1)) != hipSuccess ||
-      ensure_storage(m->cur, nbrows, nnzb, nvals) != hipSuccess)
+      ensure_storage(m->cur, nbrows, nnzb, nvals) != hipSuccess || m->dsz.ensure(4) != hipSuccess ||
+      m->norm_self.ensure(std::max(nnzb, 1)) != hipSuccess || m->frob_tmp.ensure(frobenius_tmp_elems()) != hipSuccess)
     return cleanup(BSMM_E_NOMEM, "device allocation failed");
+  const int64_t sizes[4] = {nnzb, nvals, 0, 0};
   hipError_t e = hipSuccess;
   if (nbrows) e = hipMemcpyAsync(m->d_row_sizes.p, row_sizes, sizeof(int32_t) * nbrows, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && nbcols)
@@ -250,7 +316,8 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
       e = hipMemsetAsync(m->cur.values.p, 0, sizeof(double) * nvals, s);
   }
   if (e == hipSuccess) e = hipMemsetAsync(m->cur.values.p + nvals, 0, sizeof(double) * kValueSlack, s);
-  // host buffers (rp, ci, off) die at return: finish the copies first
+  if (e == hipSuccess) e = hipMemcpyAsync(m->dsz.p, sizes, sizeof(sizes), hipMemcpyHostToDevice, s);
+  // host buffers (rp, ci, off, sizes) die at return: finish the copies first
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return cleanup(BSMM_E_HIP, std::string("create: ") + hipGetErrorString(e));
   *out = m;
@@ -281,6 +348,15 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->fvoff.release();
   m->flags.release();
   m->work.release();
+  m->class_list.release();
+  m->prod_desc.release();
+  m->split_a.release();
+  m->split_b.release();
+  m->class_cnt.release();
+  m->class_pre.release();
+  m->class_start.release();
+  m->dsz.release();
+  m->frob_tmp.release();
   if (m->h_totals) (void)hipHostFree(m->h_totals);
   drop_events(m);
   delete m;
@@ -290,8 +366,8 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
 bsmm_status bsmm_norms(bsmm_mat m, double* out, void* stream) {
   g_err.clear();
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
-  if (!out && m->nnzb > 0) return fail(BSMM_E_ARG, "NULL output");
-  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->nnzb, out,
+  if (!out && blocks_bound(m) > 0) return fail(BSMM_E_ARG, "NULL output");
+  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, blocks_bound(m), out,
                              reinterpret_cast<hipStream_t>(stream)));
   return BSMM_OK;
 }
@@ -299,6 +375,8 @@ bsmm_status bsmm_norms(bsmm_mat m, double* out, void* stream) {
 bsmm_status bsmm_info(bsmm_mat m, int32_t* nbrows, int32_t* nbcols, int32_t* nnzb, int64_t* nvals) {
   g_err.clear();
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
+  bsmm_status st = sync_sizes(m, nullptr);
+  if (st != BSMM_OK) return st;
   if (nbrows) *nbrows = m->nbrows;
   if (nbcols) *nbcols = m->nbcols;
   if (nnzb) *nnzb = m->nnzb;
@@ -312,6 +390,8 @@ bsmm_status bsmm_export(bsmm_mat m, int32_t* row_ptr, int32_t* col_idx, double* 
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
   if (ptr_kind != BSMM_PTR_HOST && ptr_kind != BSMM_PTR_DEVICE) return fail(BSMM_E_ARG, "bad ptr_kind");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bsmm_status st = sync_sizes(m, s);
+  if (st != BSMM_OK) return st;
   const hipMemcpyKind k = ptr_kind == BSMM_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   if (row_ptr) HIP_TRY(hipMemcpyAsync(row_ptr, m->cur.row_ptr.p, sizeof(int32_t) * (m->nbrows + 1), k, s));
   if (col_idx && m->nnzb) HIP_TRY(hipMemcpyAsync(col_idx, m->cur.col_idx.p, sizeof(int32_t) * m->nnzb, k, s));
@@ -325,6 +405,8 @@ bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t*
   g_err.clear();
   if (!C) return fail(BSMM_E_ARG, "NULL handle");
   if (ptr_kind != BSMM_PTR_HOST && ptr_kind != BSMM_PTR_DEVICE) return fail(BSMM_E_ARG, "bad ptr_kind");
+  bsmm_status st = sync_sizes(C, reinterpret_cast<hipStream_t>(stream));
+  if (st != BSMM_OK) return st;
   if (!C->has_stack) {
     if (nprod) *nprod = 0;
     return BSMM_OK;
@@ -390,6 +472,8 @@ bsmm_status bsmm_phase_times(bsmm_mat C, double* ms, int64_t* count) {
 bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out) {
   g_err.clear();
   if (!C || !out) return fail(BSMM_E_ARG, "NULL argument");
+  bsmm_status st = sync_sizes(C, nullptr);
+  if (st != BSMM_OK) return st;
   *out = C->stats;
   return BSMM_OK;
 }
@@ -400,7 +484,11 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   if (!A || !B || !C) return fail(BSMM_E_ARG, "NULL handle");
   if (!is_finite(alpha) || !is_finite(beta) || !is_finite(filter_eps))
     return fail(BSMM_E_ARG, "alpha, beta and filter_eps must be finite");
-  if (prec != BSMM_FP64) return fail(BSMM_E_ARG, "unknown precision");
+  if (prec != BSMM_FP64 && prec != BSMM_SPLIT_F32X2 && prec != BSMM_SPLIT_BF16X3)
+    return fail(BSMM_E_ARG, "unknown precision");
+  if (prec == BSMM_SPLIT_F32X2)
+    return fail(BSMM_E_UNSUPPORTED, "the two-term FP32 split is not built (FP32 matrix cores run at twice the FP64 "
+                                    "rate and the split needs three products, so it cannot beat FP64)");
   if (C == A || C == B) return fail(BSMM_E_ALIAS, "output must not be an input operand");
   if (A->nbcols != B->nbrows || !same_sizes(A->col_sizes, B->row_sizes))
     return fail(BSMM_E_SHAPE, "A column block sizes differ from B row block sizes");
@@ -425,8 +513,11 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     }
   }
   mark(C, ev, 0, s);
+  // Reserved output: every size stays on the device and nothing below
+  // allocates or synchronises (graph-capturable); the bounds are capacities.
+  const bool reserved = C->cap_nnzb > 0;
   // scratch
-  if (C->flags.ensure(1) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(8) != hipSuccess ||
+  if (C->flags.ensure(1) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
@@ -435,18 +526,21 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   const double* normA = nullptr;
   const double* normB = nullptr;
   if (use_eps) {
-    if (C->norm_a.ensure(std::max(A->nnzb, 1)) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
-    HIP_TRY(launch_block_norms(A->cur.blk_off.p, A->cur.values.p, A->nnzb, C->norm_a.p, s));
+    const int64_t ba = blocks_bound(A), bb = blocks_bound(B);
+    if (C->norm_a.ensure(std::max<int64_t>(ba, 1)) != hipSuccess)
+      return fail(BSMM_E_NOMEM, "scratch allocation failed");
+    HIP_TRY(launch_block_norms(A->cur.blk_off.p, A->cur.values.p, A->dsz.p, ba, C->norm_a.p, s));
     normA = C->norm_a.p;
     if (B == A) {
       normB = normA;
     } else {
-      if (C->norm_b.ensure(std::max(B->nnzb, 1)) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
-      HIP_TRY(launch_block_norms(B->cur.blk_off.p, B->cur.values.p, B->nnzb, C->norm_b.p, s));
+      if (C->norm_b.ensure(std::max<int64_t>(bb, 1)) != hipSuccess)
+        return fail(BSMM_E_NOMEM, "scratch allocation failed");
+      HIP_TRY(launch_block_norms(B->cur.blk_off.p, B->cur.values.p, B->dsz.p, bb, C->norm_b.p, s));
       normB = C->norm_b.p;
     }
   }
-  HIP_TRY(hipMemsetAsync(C->flags.p, 0, sizeof(uint32_t), s));
+  HIP_TRY(launch_zero_u32(C->flags.p, 1, s));
   mark(C, ev, 1, s);
 
   SymArgs g{};
@@ -466,6 +560,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.row_ncand = C->rows[3].p;
   g.row_nf = C->rows[4].p;
   g.flags = C->flags.p;
+  g.totals = C->totals.p;
   HIP_TRY(launch_sym_count(g, s));
   {
     const int64_t* in[5];
@@ -479,33 +574,68 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   HIP_TRY(launch_gather_totals(nbrows, C->pre[0].p, C->pre[1].p, C->pre[2].p, C->pre[3].p, C->pre[4].p,
                                C->flags.p, C->totals.p, s));
   mark(C, ev, 2, s);
-  HIP_TRY(hipMemcpyAsync(C->h_totals, C->totals.p, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const int64_t nnzc = C->h_totals[0], nprod = C->h_totals[1], nvals = C->h_totals[2], ncand = C->h_totals[3];
-  const uint32_t flags = (uint32_t)C->h_totals[4];
-  const int64_t nflop_half = C->h_totals[5];
-  if (flags & kFlagRowTooManyA)
-    return fail(BSMM_E_UNSUPPORTED, "an A block row holds more than " + std::to_string(kMaxRowA) + " blocks");
-  if (flags & kFlagRowTooManyC)
-    return fail(BSMM_E_UNSUPPORTED,
-                "a result block row would hold more than " + std::to_string(kMaxRowBlocks) + " blocks");
-  if (nnzc > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "result has more than 2^31-1 blocks");
-  if (nprod > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "more than 2^31-1 block products");
+
+  int64_t nnzc = 0, nprod = 0, nvals = 0, ncand = 0, nflop_half = 0;
+  int64_t nnzc_bound, nprod_bound, nvals_bound;
+  if (reserved) {
+    HIP_TRY(launch_check_capacity(C->totals.p, C->cap_nnzb, C->cap_nvals, C->cap_nprod, s));
+    nnzc_bound = C->cap_nnzb;
+    nprod_bound = C->cap_nprod;
+    nvals_bound = C->cap_nvals;
+  } else {
+    HIP_TRY(hipMemcpyAsync(C->h_totals, C->totals.p, kTotCount * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    nnzc = C->h_totals[kTotNnzc];
+    nprod = C->h_totals[kTotNprod];
+    nvals = C->h_totals[kTotNvals];
+    ncand = C->h_totals[kTotCand];
+    nflop_half = C->h_totals[kTotFlopHalf];
+    const uint32_t flags = (uint32_t)C->h_totals[kTotFlags];
+    if (flags & kFlagRowTooManyA)
+      return fail(BSMM_E_UNSUPPORTED, "an A block row holds more than " + std::to_string(kMaxRowA) + " blocks");
+    if (flags & kFlagRowTooManyC)
+      return fail(BSMM_E_UNSUPPORTED,
+                  "a result block row would hold more than " + std::to_string(kMaxRowBlocks) + " blocks");
+    if (nnzc > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "result has more than 2^31-1 blocks");
+    if (nprod > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "more than 2^31-1 block products");
+    nnzc_bound = nnzc;
+    nprod_bound = nprod;
+    nvals_bound = nvals;
+  }
 
   // output storage: in place -> write the spare storage and swap afterwards
   const bool in_place = use_old && C_in == C;
   Storage& out = in_place ? C->spare : C->cur;
-  if (ensure_storage(out, nbrows, nnzc, nvals) != hipSuccess || C->prod_ptr.ensure(nnzc + 1) != hipSuccess ||
-      C->prod_a.ensure(std::max<int64_t>(nprod, 1)) != hipSuccess ||
-      C->prod_b.ensure(std::max<int64_t>(nprod, 1)) != hipSuccess ||
-      C->old_idx.ensure(std::max<int64_t>(nnzc, 1)) != hipSuccess)
+  if (ensure_storage(out, nbrows, nnzc_bound, nvals_bound) != hipSuccess ||
+      C->prod_ptr.ensure(nnzc_bound + 1) != hipSuccess ||
+      C->prod_a.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
+      C->prod_b.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
+      C->old_idx.ensure(std::max<int64_t>(nnzc_bound, 1)) != hipSuccess)
     return fail(BSMM_E_NOMEM, "device allocation for the result failed");
+  const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
+  const bool split = prec == BSMM_SPLIT_BF16X3;
+  const bool small = !split && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
+  if (split) {
+    if (uniform != 23) return fail(BSMM_E_UNSUPPORTED, "split precision is built for uniform 23x23 blocks");
+    if (C->split_a.ensure(split_elems(std::max<int64_t>(blocks_bound(A), 1))) != hipSuccess ||
+        C->split_b.ensure(split_elems(std::max<int64_t>(blocks_bound(B), 1))) != hipSuccess)
+      return fail(BSMM_E_NOMEM, "device allocation for the split operands failed");
+  }
+  if (small) {
+    const int64_t ncl = class_list_tmp_elems(nnzc_bound);
+    if (C->class_list.ensure(2 * std::max<int64_t>(nnzc_bound, 1)) != hipSuccess ||
+        C->prod_desc.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
+        C->class_cnt.ensure(ncl) != hipSuccess || C->class_pre.ensure(ncl) != hipSuccess ||
+        C->class_start.ensure(5) != hipSuccess ||
+        C->scan_tmp.ensure(std::max(scan_tmp_elems(nbrows), scan_tmp_elems(ncl)) + 2) != hipSuccess)
+      return fail(BSMM_E_NOMEM, "device allocation for the block classes failed");
+  }
   // a reallocation above may have freed C_in's storage only if C_in == C and
   // `out` is cur; that case is excluded by writing the spare.
   if (use_old) g.Cin = view(C_in);
   mark(C, ev, 3, s);
   HIP_TRY(launch_finish_rows(nbrows, C->pre[0].p, C->pre[1].p, C->pre[2].p, out.row_ptr.p, C->prod_ptr.p,
-                             out.blk_off.p, s));
+                             out.blk_off.p, C->totals.p, s));
   g.c_row_ptr = out.row_ptr.p;
   g.row_pstart = C->pre[1].p;
   g.row_vstart = C->pre[2].p;
@@ -515,6 +645,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.c_old_idx = C->old_idx.p;
   g.prod_a = C->prod_a.p;
   g.prod_b = C->prod_b.p;
+  g.desc = small ? C->prod_desc.p : nullptr;
   HIP_TRY(launch_sym_fill(g, s));
   mark(C, ev, 4, s);
 
@@ -525,7 +656,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.use_old = g.use_old;
   na.alpha = alpha;
   na.beta = beta;
-  na.nnzc = (int32_t)nnzc;
+  na.nnzc_bound = nnzc_bound;
+  na.totals = C->totals.p;
   na.c_row_sizes = C->d_row_sizes.p;
   na.c_col_sizes = C->d_col_sizes.p;
   na.c_col_idx = out.col_idx.p;
@@ -535,22 +667,34 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_a = C->prod_a.p;
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
-  const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
-  HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
+  if (split) {
+    HIP_TRY(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
+    HIP_TRY(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
+    HIP_TRY(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
+  } else if (small) {
+    HIP_TRY(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
+                               C->class_start.p, s));
+    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->prod_desc.p, s));
+  } else {
+    HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
+  }
   mark(C, ev, 5, s);
-  HIP_TRY(hipMemsetAsync(out.values.p + nvals, 0, sizeof(double) * kValueSlack, s));
+  HIP_TRY(launch_finish_multiply(C->totals.p, out.values.p, C->dsz.p, s));
   mark(C, ev, 6, s);
 
   if (in_place) std::swap(C->cur, C->spare);
+  C->has_stack = true;
+  if (reserved) return BSMM_OK;
   C->nnzb = (int32_t)nnzc;
   C->nvals = nvals;
   C->nprod = nprod;
-  C->has_stack = true;
   C->stats.candidates = ncand;
   C->stats.products = nprod;
   C->stats.nnzb = nnzc;
   C->stats.nvals = nvals;
   C->stats.useful_flops = 2.0 * (double)nflop_half;
+  if (C->norm_self.ensure(std::max<int64_t>(nnzc, 1)) != hipSuccess)
+    return fail(BSMM_E_NOMEM, "scratch allocation failed");
   return BSMM_OK;
 }
 
@@ -561,25 +705,150 @@ bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   bsmm_status st = ensure_pinned(m);
   if (st != BSMM_OK) return st;
-  const int32_t nnzb = m->nnzb;
-  if (m->norm_self.ensure(std::max(nnzb, 1)) != hipSuccess || m->fkeep.ensure(nnzb + 1) != hipSuccess ||
-      m->fvsz.ensure(nnzb + 1) != hipSuccess || m->fpos.ensure(nnzb + 1) != hipSuccess ||
-      m->fvoff.ensure(nnzb + 1) != hipSuccess || m->scan_tmp.ensure(scan_tmp_elems(nnzb) + 2) != hipSuccess ||
-      ensure_storage(m->spare, m->nbrows, nnzb, m->nvals) != hipSuccess)
+  const bool reserved = m->cap_nnzb > 0;
+  const int64_t bound = reserved ? m->cap_nnzb : m->nnzb;
+  const int64_t vbound = reserved ? m->cap_nvals : m->nvals;
+  if (m->norm_self.ensure(std::max<int64_t>(bound, 1)) != hipSuccess || m->fkeep.ensure(bound + 1) != hipSuccess ||
+      m->fvsz.ensure(bound + 1) != hipSuccess || m->fpos.ensure(bound + 1) != hipSuccess ||
+      m->fvoff.ensure(bound + 1) != hipSuccess ||
+      m->scan_tmp.ensure(std::max(scan_tmp_elems(bound), scan_tmp_elems(m->nbrows)) + 2) != hipSuccess ||
+      ensure_storage(m->spare, m->nbrows, bound, vbound) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
-  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, nnzb, m->norm_self.p, s));
-  HIP_TRY(launch_filter(m->cur.row_ptr.p, m->cur.col_idx.p, m->cur.blk_off.p, m->cur.values.p, m->nbrows, nnzb,
-                        m->norm_self.p, eps, m->fkeep.p, m->fvsz.p, m->fpos.p, m->fvoff.p, m->scan_tmp.p,
+  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, bound, m->norm_self.p, s));
+  HIP_TRY(launch_filter(m->cur.row_ptr.p, m->cur.col_idx.p, m->cur.blk_off.p, m->cur.values.p, m->nbrows, m->dsz.p,
+                        bound, m->norm_self.p, eps, m->fkeep.p, m->fvsz.p, m->fpos.p, m->fvoff.p, m->scan_tmp.p,
                         m->spare.row_ptr.p, m->spare.col_idx.p, m->spare.blk_off.p, m->spare.values.p, s));
-  HIP_TRY(hipMemcpyAsync(m->h_totals, m->fpos.p + nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(m->h_totals + 1, m->fvoff.p + nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const int64_t new_nnzb = m->h_totals[0], new_nvals = m->h_totals[1];
-  HIP_TRY(hipMemsetAsync(m->spare.values.p + new_nvals, 0, sizeof(double) * kValueSlack, s));
   std::swap(m->cur, m->spare);
-  m->nnzb = (int32_t)new_nnzb;
-  m->nvals = new_nvals;
   m->has_stack = false;  // block indices changed
+  if (reserved) return BSMM_OK;
+  HIP_TRY(hipMemcpyAsync(m->h_totals, m->dsz.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  m->nnzb = (int32_t)m->h_totals[0];
+  m->nvals = m->h_totals[1];
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_t max_products, void* stream) {
+  g_err.clear();
+  if (!m) return fail(BSMM_E_ARG, "NULL handle");
+  if (max_nnzb < 1 || max_nvals < 1 || max_products < 1) return fail(BSMM_E_ARG, "capacities must be >= 1");
+  if (max_nnzb > 0x7fffffffLL || max_products > 0x7fffffffLL)
+    return fail(BSMM_E_CAPACITY, "block and product capacities are limited to 2^31-1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bsmm_status st = sync_sizes(m, s);
+  if (st != BSMM_OK) return st;
+  st = ensure_pinned(m);
+  if (st != BSMM_OK) return st;
+  const int64_t cb = std::max<int64_t>(max_nnzb, m->nnzb), cv = std::max<int64_t>(max_nvals, m->nvals);
+  const int64_t cp = max_products;
+  const int32_t nbrows = m->nbrows;
+  // grow the current storage without losing its contents
+  if (m->cur.col_idx.cap < cb || m->cur.blk_off.cap < cb + 1 || m->cur.values.cap < cv + kValueSlack) {
+    Storage fresh;
+    if (ensure_storage(fresh, nbrows, cb, cv) != hipSuccess) {
+      fresh.release();
+      return fail(BSMM_E_NOMEM, "device allocation for the reservation failed");
+    }
+    HIP_TRY(hipMemcpyAsync(fresh.row_ptr.p, m->cur.row_ptr.p, sizeof(int32_t) * (nbrows + 1),
+                           hipMemcpyDeviceToDevice, s));
+    if (m->nnzb)
+      HIP_TRY(hipMemcpyAsync(fresh.col_idx.p, m->cur.col_idx.p, sizeof(int32_t) * m->nnzb, hipMemcpyDeviceToDevice,
+                             s));
+    HIP_TRY(hipMemcpyAsync(fresh.blk_off.p, m->cur.blk_off.p, sizeof(int64_t) * (m->nnzb + 1),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(fresh.values.p, m->cur.values.p, sizeof(double) * (m->nvals + kValueSlack),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    m->cur.release();
+    m->cur = fresh;
+  }
+  const int64_t ncl = class_list_tmp_elems(cb);
+  const int64_t tmp = std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(cb)}) + 2;
+  bool ok = ensure_storage(m->spare, nbrows, cb, cv) == hipSuccess && m->prod_ptr.ensure(cb + 1) == hipSuccess &&
+            m->prod_a.ensure(cp) == hipSuccess && m->prod_b.ensure(cp) == hipSuccess &&
+            m->old_idx.ensure(cb) == hipSuccess && m->prod_desc.ensure(cp) == hipSuccess &&
+            m->class_list.ensure(2 * cb) == hipSuccess && m->class_cnt.ensure(ncl) == hipSuccess &&
+            m->class_pre.ensure(ncl) == hipSuccess && m->class_start.ensure(5) == hipSuccess &&
+            m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
+            m->flags.ensure(1) == hipSuccess && m->work.ensure(1) == hipSuccess &&
+            m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&
+            m->norm_self.ensure(cb) == hipSuccess && m->fkeep.ensure(cb + 1) == hipSuccess &&
+            m->fvsz.ensure(cb + 1) == hipSuccess && m->fpos.ensure(cb + 1) == hipSuccess &&
+            m->fvoff.ensure(cb + 1) == hipSuccess && m->split_a.ensure(split_elems(cb)) == hipSuccess &&
+            m->split_b.ensure(split_elems(cb)) == hipSuccess;
+  for (int x = 0; x < 5 && ok; ++x)
+    ok = m->rows[x].ensure(nbrows + 1) == hipSuccess && m->pre[x].ensure(nbrows + 1) == hipSuccess;
+  if (!ok) return fail(BSMM_E_NOMEM, "device allocation for the reservation failed");
+  // counters read back before the first reserved multiply: zero
+  if (!m->has_stack) {
+    HIP_TRY(hipMemsetAsync(m->totals.p, 0, kTotCount * sizeof(int64_t), s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    const int64_t t[kTotCount] = {m->stats.nnzb, m->nprod, m->stats.nvals, m->stats.candidates, 0,
+                                  (int64_t)(m->stats.useful_flops / 2), 0, 0};
+    HIP_TRY(hipMemcpyAsync(m->totals.p, t, sizeof(t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  m->cap_nnzb = cb;
+  m->cap_nvals = cv;
+  m->cap_nprod = cp;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_frobenius(bsmm_mat m, double* out, void* stream) {
+  g_err.clear();
+  if (!m || !out) return fail(BSMM_E_ARG, "NULL argument");
+  HIP_TRY(launch_frobenius(m->cur.values.p, m->dsz.p + 1, m->frob_tmp.p, out, reinterpret_cast<hipStream_t>(stream)));
+  return BSMM_OK;
+}
+
+struct bsmm_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+bsmm_status bsmm_capture_begin(void* stream) {
+  g_err.clear();
+  if (!stream) return fail(BSMM_E_ARG, "capture needs a created stream, not the default stream");
+  HIP_TRY(hipStreamBeginCapture(reinterpret_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal));
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_capture_end(void* stream, bsmm_graph* out) {
+  g_err.clear();
+  if (!stream || !out) return fail(BSMM_E_ARG, "NULL argument");
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamEndCapture(reinterpret_cast<hipStream_t>(stream), &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(BSMM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  bsmm_graph g = new (std::nothrow) bsmm_graph_s();
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(BSMM_E_NOMEM, "host allocation failed");
+  }
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_graph_launch(bsmm_graph g, void* stream) {
+  g_err.clear();
+  if (!g) return fail(BSMM_E_ARG, "NULL graph");
+  HIP_TRY(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_graph_destroy(bsmm_graph g) {
+  if (!g) return BSMM_OK;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
   return BSMM_OK;
 }
 

@@ -31,6 +31,28 @@ enum : uint32_t {
   kFlagRowTooManyA = 1u,      // an A block row has more than kMaxRowA blocks
   kFlagRowTooManyC = 2u,      // a C block row has more than kMaxRowBlocks blocks
 };
+// Error bits of a matrix's size record (dsz[2]); the row flags above too.
+constexpr int64_t kErrCapacity = 4;  // a result did not fit the reserved capacity
+
+// Slots of the per-multiply totals array (device int64).
+enum : int {
+  kTotNnzc = 0,      // result blocks
+  kTotNprod = 1,     // kept block products
+  kTotNvals = 2,     // result values
+  kTotCand = 3,      // candidate products before the filter
+  kTotFlags = 4,     // symbolic-pass flags
+  kTotFlopHalf = 5,  // sum over kept products of m*n*k
+  kTotAbort = 6,     // nonzero: the result does not fit; later kernels do nothing
+  kTotCount = 8
+};
+
+// Doubles of zero slack kept after the last value of every matrix.
+constexpr int kValueSlackDoubles = 64;
+
+// Result blocks of the multiply whose totals these are (0 once aborted).
+__device__ __forceinline__ int32_t live_nnzc(const int64_t* totals) {
+  return totals[kTotAbort] ? 0 : (int32_t)totals[kTotNnzc];
+}
 
 // Inputs of the symbolic phase.
 struct SymArgs {
@@ -59,13 +81,17 @@ struct SymArgs {
   int32_t* c_old_idx;   // [nnzc] block of C_in or -1
   int32_t* prod_a;      // [nprod]
   int32_t* prod_b;      // [nprod]
+  // optional (small-block path): per product {A value offset | k << 56, B value offset}
+  int4* desc;
+  const int64_t* totals;  // per-multiply totals (the fill does nothing once aborted)
 };
 
 struct NumArgs {
   MatView A, B, Cin;
   int use_old;
   double alpha, beta;
-  int32_t nnzc;
+  int64_t nnzc_bound;      // host bound on the result blocks (exact, or the reserved capacity)
+  const int64_t* totals;   // device totals: the result block count, abort flag
   const int32_t* c_row_sizes;
   const int32_t* c_col_sizes;
   const int32_t* c_col_idx;
@@ -78,8 +104,20 @@ struct NumArgs {
 };
 
 // Launchers (all enqueue on `s`; they return the launch status).
-hipError_t launch_block_norms(const int64_t* blk_off, const double* values, int32_t nnzb, double* out,
-                              hipStream_t s);
+// Norms of the first *d_nnzb blocks; bound >= *d_nnzb sizes the launch.
+hipError_t launch_block_norms(const int64_t* blk_off, const double* values, const int64_t* d_nnzb, int64_t bound,
+                              double* out, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+// Zero the value slack after the result and write its size record
+// dsz = {nnzb, nvals, error bits}.
+hipError_t launch_finish_multiply(const int64_t* totals, double* values, int64_t* dsz, hipStream_t s);
+hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_nvals, int64_t cap_nprod,
+                                 hipStream_t s);
+// Frobenius norm of the first *d_nvals values into out[0] (device); partial
+// needs frobenius_tmp_elems() doubles.
+int64_t frobenius_tmp_elems();
+hipError_t launch_frobenius(const double* values, const int64_t* d_nvals, double* partial, double* out,
+                            hipStream_t s);
 
 // Device-wide exclusive scan of n int64 values into out[0..n] (out[n] = total).
 // tmp must hold scan_tmp_elems(n) entries; in and out must not overlap.
@@ -92,16 +130,39 @@ hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, in
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s);
 hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s);
 hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
-                              int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, hipStream_t s);
+                              int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, const int64_t* totals,
+                              hipStream_t s);
 hipError_t launch_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
                                 const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
                                 int64_t* totals, hipStream_t s);
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s);
 
-// filter(M, eps): keep/vsz/keep_pos/voff are scratch of nnzb (+1) entries.
+// Small-block path (every block edge <= kSmallEdge): C blocks are partitioned
+// by padded shape class, then one persistent launch multiplies all classes.
+constexpr int kSmallEdge = 16;
+int64_t class_list_tmp_elems(int64_t nnzc_bound);  // entries of cnt and cnt_pre
+// list holds two int4 per C block: {m | n << 8, first product, product count, 0}
+// and {C value offset, C_in value offset or -1} (int64 pairs).
+hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, int64_t* tmp, int4* list,
+                              int32_t* cls_start, hipStream_t s);
+hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int4* desc,
+                                hipStream_t s);
+
+// Split precision (23x23 blocks): FP64 values -> three BF16 terms per value,
+// split_elems(nblocks) uint16 per matrix; transpose = 1 stores each block
+// transposed (the B operand).  The numeric kernel multiplies the terms on
+// BF16 matrix cores and accumulates each block product into FP64.
+int64_t split_elems(int64_t nblocks);
+hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int64_t bound, int transpose,
+                               uint16_t* out, hipStream_t s);
+hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, hipStream_t s);
+
+// filter(M, eps) over the first dsz[0] blocks (bound >= dsz[0] sizes the
+// launches; keep/vsz/keep_pos/voff are scratch of bound (+1) entries).  The
+// new sizes replace dsz[0..1].
 hipError_t launch_filter(const int32_t* row_ptr, const int32_t* col_idx, const int64_t* blk_off,
-                         const double* values, int32_t nbrows, int32_t nnzb, const double* norms, double eps,
-                         int64_t* keep, int64_t* vsz, int64_t* keep_pos, int64_t* voff, int64_t* tmp,
+                         const double* values, int32_t nbrows, int64_t* dsz, int64_t bound, const double* norms,
+                         double eps, int64_t* keep, int64_t* vsz, int64_t* keep_pos, int64_t* voff, int64_t* tmp,
                          int32_t* out_row_ptr, int32_t* out_col_idx, int64_t* out_blk_off,
                          double* out_values, hipStream_t s);
 

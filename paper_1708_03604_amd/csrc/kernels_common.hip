@@ -11,9 +11,11 @@ namespace bsmm {
 // ---------------------------------------------------------------- norms
 
 __global__ __launch_bounds__(256) void k_block_norms(const int64_t* __restrict__ blk_off,
-                                                     const double* __restrict__ values, int32_t nnzb,
+                                                     const double* __restrict__ values,
+                                                     const int64_t* __restrict__ d_nnzb,
                                                      double* __restrict__ out) {
   const int lane = threadIdx.x & 63;
+  const int32_t nnzb = (int32_t)*d_nnzb;
   const int32_t nwaves = gridDim.x * (blockDim.x >> 6);
   for (int32_t b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nnzb; b += nwaves) {
     const int64_t o = blk_off[b];
@@ -30,12 +32,12 @@ __global__ __launch_bounds__(256) void k_block_norms(const int64_t* __restrict__
   }
 }
 
-hipError_t launch_block_norms(const int64_t* blk_off, const double* values, int32_t nnzb, double* out,
-                              hipStream_t s) {
-  if (nnzb <= 0) return hipSuccess;
-  int32_t blocks = (nnzb + 3) / 4;
+hipError_t launch_block_norms(const int64_t* blk_off, const double* values, const int64_t* d_nnzb, int64_t bound,
+                              double* out, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
+  int64_t blocks = (bound + 3) / 4;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_block_norms, dim3(blocks), dim3(256), 0, s, blk_off, values, nnzb, out);
+  hipLaunchKernelGGL(k_block_norms, dim3((uint32_t)blocks), dim3(256), 0, s, blk_off, values, d_nnzb, out);
   return hipGetLastError();
 }
 
@@ -193,6 +195,101 @@ __global__ __launch_bounds__(kRowScanThreads) void k_scan_rows(ScanSet set, int 
   if (threadIdx.x < narr) set.out[threadIdx.x][n] = carry[threadIdx.x];
 }
 
+// ---------------------------------------------------------------- small helpers
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// Multiply epilogue on the device: zero the value slack after the result and
+// record the result's sizes (or the error) in the output's size record.
+__global__ void k_finish_multiply(const int64_t* __restrict__ totals, double* __restrict__ values,
+                                  int64_t* __restrict__ dsz) {
+  const int t = threadIdx.x;
+  const bool ok = totals[kTotAbort] == 0;
+  if (ok && t < kValueSlackDoubles) values[totals[kTotNvals] + t] = 0.0;
+  if (t == 0) {
+    dsz[0] = ok ? totals[kTotNnzc] : 0;
+    dsz[1] = ok ? totals[kTotNvals] : 0;
+    dsz[2] = ok ? 0 : (totals[kTotFlags] | kErrCapacity * (totals[kTotFlags] == 0));
+  }
+}
+
+hipError_t launch_finish_multiply(const int64_t* totals, double* values, int64_t* dsz, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_multiply, dim3(1), dim3(64), 0, s, totals, values, dsz);
+  return hipGetLastError();
+}
+
+// Reserved capacity check: raises totals[kTotAbort] if the result does not fit
+// (or the symbolic pass flagged a row); every later kernel then does nothing.
+__global__ void k_check_capacity(int64_t* __restrict__ totals, int64_t cap_nnzb, int64_t cap_nvals,
+                                 int64_t cap_nprod) {
+  if (threadIdx.x != 0) return;
+  const bool bad = totals[kTotFlags] != 0 || totals[kTotNnzc] > cap_nnzb || totals[kTotNvals] > cap_nvals ||
+                   totals[kTotNprod] > cap_nprod || totals[kTotNnzc] > 0x7fffffffLL ||
+                   totals[kTotNprod] > 0x7fffffffLL;
+  totals[kTotAbort] = bad ? 1 : 0;
+}
+
+hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_nvals, int64_t cap_nprod,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, totals, cap_nnzb, cap_nvals, cap_nprod);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Frobenius norm
+
+// Fixed-order sum of squares: workgroup g sums a contiguous slice of the
+// values (thread t takes every 256th element from t, fused multiply-add),
+// then a pairwise tree over the 256 threads; the final pass adds the
+// per-workgroup partials the same way and takes the square root.
+constexpr int kFrobGroups = 256;
+
+__device__ double block_tree_sum(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int d = 128; d >= 1; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + d];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_frob_partial(const double* __restrict__ values,
+                                                      const int64_t* __restrict__ d_nvals,
+                                                      double* __restrict__ partial) {
+  const int64_t n = *d_nvals;
+  const int64_t per = (n + kFrobGroups - 1) / kFrobGroups;
+  const int64_t b0 = per * blockIdx.x;
+  const int64_t b1 = b0 + per < n ? b0 + per : n;
+  double p = 0.0;
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) p = fma(values[e], values[e], p);
+  const double t = block_tree_sum(p);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_frob_final(const double* __restrict__ partial, double* __restrict__ out) {
+  const double t = block_tree_sum(partial[threadIdx.x]);
+  if (threadIdx.x == 0) out[0] = sqrt(t);
+}
+
+int64_t frobenius_tmp_elems() { return kFrobGroups; }
+
+hipError_t launch_frobenius(const double* values, const int64_t* d_nvals, double* partial, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_frob_partial, dim3(kFrobGroups), dim3(256), 0, s, values, d_nvals, partial);
+  hipLaunchKernelGGL(k_frob_final, dim3(1), dim3(256), 0, s, partial, out);
+  return hipGetLastError();
+}
+
 hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, int64_t n, int64_t* tmp,
                      hipStream_t s) {
   if (n > (1 << 16)) {
@@ -214,19 +311,24 @@ hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, in
 // ---------------------------------------------------------------- filter
 
 // keep[b] = 1 if eps <= 0 or norm > eps; vsz[b] = its value count if kept.
+// Entries from the matrix's block count up to the launch bound are zero, so
+// the scans may run over the bound.
 __global__ __launch_bounds__(256) void k_filter_flags(const int64_t* __restrict__ blk_off,
-                                                      const double* __restrict__ norms, int32_t nnzb,
+                                                      const double* __restrict__ norms,
+                                                      const int64_t* __restrict__ d_nnzb, int64_t bound,
                                                       double eps, int64_t* __restrict__ keep,
                                                       int64_t* __restrict__ vsz) {
-  const int32_t b = blockIdx.x * 256 + threadIdx.x;
-  if (b >= nnzb) return;
-  const bool k = (eps <= 0.0) || (norms[b] > eps);
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= bound) return;
+  const bool live = b < *d_nnzb;
+  const bool k = live && ((eps <= 0.0) || (norms[b] > eps));
   keep[b] = k ? 1 : 0;
   vsz[b] = k ? (blk_off[b + 1] - blk_off[b]) : 0;
 }
 
 // One wave per source block: copy kept blocks to their compacted position.
-__global__ __launch_bounds__(256) void k_filter_compact(int32_t nnzb, const int64_t* __restrict__ keep_pos,
+__global__ __launch_bounds__(256) void k_filter_compact(const int64_t* __restrict__ d_nnzb,
+                                                        const int64_t* __restrict__ keep_pos,
                                                         const int64_t* __restrict__ voff,
                                                         const int32_t* __restrict__ col_idx,
                                                         const int64_t* __restrict__ blk_off,
@@ -235,6 +337,7 @@ __global__ __launch_bounds__(256) void k_filter_compact(int32_t nnzb, const int6
                                                         int64_t* __restrict__ out_blk_off,
                                                         double* __restrict__ out_values) {
   const int lane = threadIdx.x & 63;
+  const int32_t nnzb = (int32_t)*d_nnzb;
   const int32_t nwaves = gridDim.x * 4;
   for (int32_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nnzb; b += nwaves) {
     const int64_t pos = keep_pos[b];
@@ -256,26 +359,41 @@ __global__ __launch_bounds__(256) void k_filter_rowptr(int32_t nbrows, const int
   if (i <= nbrows) out_row_ptr[i] = (int32_t)keep_pos[row_ptr[i]];
 }
 
+// New sizes into the size record (in place: d_nnzb may be dsz itself), and
+// zero slack after the new values.
+__global__ void k_filter_finish(const int64_t* __restrict__ keep_pos, const int64_t* __restrict__ voff,
+                                int64_t bound, double* __restrict__ out_values, int64_t* __restrict__ dsz) {
+  const int64_t nv = voff[bound];
+  const int t = threadIdx.x;
+  if (t < kValueSlackDoubles) out_values[nv + t] = 0.0;
+  __syncthreads();
+  if (t == 0) {
+    dsz[0] = keep_pos[bound];
+    dsz[1] = nv;
+  }
+}
+
 hipError_t launch_filter(const int32_t* row_ptr, const int32_t* col_idx, const int64_t* blk_off,
-                         const double* values, int32_t nbrows, int32_t nnzb, const double* norms, double eps,
-                         int64_t* keep, int64_t* vsz, int64_t* keep_pos, int64_t* voff, int64_t* tmp,
+                         const double* values, int32_t nbrows, int64_t* dsz, int64_t bound, const double* norms,
+                         double eps, int64_t* keep, int64_t* vsz, int64_t* keep_pos, int64_t* voff, int64_t* tmp,
                          int32_t* out_row_ptr, int32_t* out_col_idx, int64_t* out_blk_off,
                          double* out_values, hipStream_t s) {
-  if (nnzb > 0) {
-    hipLaunchKernelGGL(k_filter_flags, dim3((nnzb + 255) / 256), dim3(256), 0, s, blk_off, norms, nnzb, eps,
-                       keep, vsz);
+  if (bound > 0) {
+    hipLaunchKernelGGL(k_filter_flags, dim3((uint32_t)((bound + 255) / 256)), dim3(256), 0, s, blk_off, norms, dsz,
+                       bound, eps, keep, vsz);
   }
-  hipError_t e = scan_exclusive(keep, nnzb, keep_pos, tmp, s);
+  hipError_t e = scan_exclusive(keep, bound, keep_pos, tmp, s);
   if (e != hipSuccess) return e;
-  e = scan_exclusive(vsz, nnzb, voff, tmp, s);
+  e = scan_exclusive(vsz, bound, voff, tmp, s);
   if (e != hipSuccess) return e;
-  int32_t blocks = (nnzb + 3) / 4;
+  int64_t blocks = (bound + 3) / 4;
   if (blocks > 16384) blocks = 16384;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_filter_compact, dim3(blocks), dim3(256), 0, s, nnzb, keep_pos, voff, col_idx, blk_off,
-                     values, out_col_idx, out_blk_off, out_values);
+  hipLaunchKernelGGL(k_filter_compact, dim3((uint32_t)blocks), dim3(256), 0, s, dsz, keep_pos, voff, col_idx,
+                     blk_off, values, out_col_idx, out_blk_off, out_values);
   hipLaunchKernelGGL(k_filter_rowptr, dim3((nbrows + 1 + 255) / 256), dim3(256), 0, s, nbrows, row_ptr, keep_pos,
                      out_row_ptr);
+  hipLaunchKernelGGL(k_filter_finish, dim3(1), dim3(64), 0, s, keep_pos, voff, bound, out_values, dsz);
   return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@ namespace bsmm {
 __global__ __launch_bounds__(256) void k_numeric_generic(NumArgs g) {
   const int lane = threadIdx.x & 63;
   const int32_t nwaves = gridDim.x * 4;
-  for (int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < g.nnzc; c += nwaves) {
+  const int32_t nnzc = live_nnzc(g.totals);
+  for (int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < nnzc; c += nwaves) {
     const int32_t n = g.c_col_sizes[g.c_col_idx[c]];
     const int64_t off = g.c_blk_off[c];
     const int64_t mn = g.c_blk_off[c + 1] - off;
@@ -110,8 +111,8 @@ template <int S>
 __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
     const double* __restrict__ Av, const double* __restrict__ Bv, const double* __restrict__ Ov,
     const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
-    const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, int32_t nnzc, int use_old, double alpha,
-    double beta) {
+    const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals, int use_old,
+    double alpha, double beta) {
   static_assert(S >= 13 && S <= kTileEdge, "tile kernel covers edges 13..24");
   constexpr int NE = S * S;
   constexpr int PER = (NE + 63) / 64;
@@ -148,6 +149,8 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;  // waves per XCD
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
+  const int32_t nnzc = live_nnzc(totals);
+  if (nnzc == 0) return;
   const int64_t P = prod_ptr[nnzc];
   const int32_t X0 = lower_bound_c(prod_ptr, nnzc, P * xcd / kXcds);
   const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_c(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
 }
 
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s) {
-  if (a.nnzc <= 0) return hipSuccess;
+  if (a.nnzc_bound <= 0) return hipSuccess;
   (void)work;
   if (uniform_size == 23) {
     int dev = 0, cus = 256;
@@ -353,12 +356,12 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
     blocks = ((blocks + 7) / 8) * 8;
     hipLaunchKernelGGL(k_numeric_tile24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
                        a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
-                       a.c_values, a.nnzc, a.use_old, a.alpha, a.beta);
+                       a.c_values, a.totals, a.use_old, a.alpha, a.beta);
     return hipGetLastError();
   }
-  int32_t blocks = (a.nnzc + 3) / 4;
+  int64_t blocks = (a.nnzc_bound + 3) / 4;
   if (blocks > 32768) blocks = 32768;
-  hipLaunchKernelGGL(k_numeric_generic, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_numeric_generic, dim3((uint32_t)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

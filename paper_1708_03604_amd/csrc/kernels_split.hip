@@ -1,0 +1,324 @@
+// Split-precision block products for 23x23 blocks on BF16 matrix cores.
+//
+// Every FP64 operand value x is split once per multiply into three BF16
+// terms, x ~ s0 + s1 + s2 with s0 = bf16(x), s1 = bf16(x - s0),
+// s2 = bf16(x - s0 - s1) (round to nearest even; the residuals are exact in
+// FP64).  A block product keeps the six term products s_i(a) s_j(b) with
+// i + j <= 2, on v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the FP32
+// result of each block product is added to an FP64 accumulator, and the C
+// block is finished in FP64 (alpha, beta, C_in).  Norms, the filter and the
+// symbolic phase stay FP64 (they run before this kernel, unchanged).
+//
+// Storage of the split terms (per block, 16-byte aligned): three slices of
+// 23 rows x 24 BF16 (the 24th column zero), 3312 bytes instead of the 4232
+// bytes of the FP64 block.  A is stored as is (row i holds A(i, :)), B
+// transposed (row j holds B(:, j)), so both MFMA operands read 8 consecutive
+// inner indices with one 16-byte LDS load.
+#include <type_traits>
+
+#include "bsmm_internal.h"
+
+namespace bsmm {
+
+namespace {
+
+constexpr int kE = 23;                     // block edge
+constexpr int kRowPad = 24;                // BF16 per stored row
+constexpr int kSlice = kE * kRowPad;       // 552 BF16 per slice
+constexpr int kSplitBlock = 3 * kSlice;    // 1656 BF16 = 3312 bytes per block
+constexpr int kChunks = kSplitBlock * 2 / 16;  // 207 16-byte chunks per block
+constexpr int kChunksPerSlice = kSlice * 2 / 16;  // 69
+constexpr int kLdsRow = 80;                // bytes per LDS row (32 BF16 + pad)
+constexpr int kLdsSlice = 32 * kLdsRow;    // 2560 bytes: 32 rows, rows 23..31 zero
+constexpr int kLdsOperand = 3 * kLdsSlice; // 7680 bytes
+constexpr int kLdsStage = 2 * kLdsOperand; // 15360 bytes: A slices then B^T slices
+constexpr int kPer = (kChunks + 63) / 64;  // 4 chunk loads per lane and operand
+constexpr int kLast = kChunks - 64 * (kPer - 1);  // lanes with a 4th chunk: 15
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// float -> bf16 bits, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ double bf16_value(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
+
+// One thread per stored BF16 position of every block: (block, row, col).
+__global__ __launch_bounds__(256) void k_split_bf16x3(const double* __restrict__ values,
+                                                      const int64_t* __restrict__ d_nnzb, int transpose,
+                                                      uint16_t* __restrict__ out) {
+  const int64_t nnzb = *d_nnzb;
+  const int64_t total = nnzb * kSlice;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int64_t b = t / kSlice;
+    const int rc = (int)(t - b * kSlice);
+    const int r = rc / kRowPad, c = rc - r * kRowPad;  // stored row r, column c
+    double x = 0.0;
+    if (c < kE) x = transpose ? values[b * kE * kE + c * kE + r] : values[b * kE * kE + r * kE + c];
+    const uint16_t h0 = bf16_bits((float)x);
+    const double r1 = x - bf16_value(h0);
+    const uint16_t h1 = bf16_bits((float)r1);
+    const double r2 = r1 - bf16_value(h1);
+    const uint16_t h2 = bf16_bits((float)r2);
+    uint16_t* o = out + b * kSplitBlock + rc;
+    o[0] = h0;
+    o[kSlice] = h1;
+    o[2 * kSlice] = h2;
+  }
+}
+
+__device__ __forceinline__ int64_t uniform64s(int64_t x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int32_t lower_bound_cs(const int64_t* prod_ptr, int32_t n, int64_t t) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = __builtin_amdgcn_readfirstlane((lo + hi) >> 1);
+    if (prod_ptr[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Schedule as in the FP64 23x23 kernel: each XCD owns a contiguous run of C
+// blocks holding 1/8 of the products; its waves take interleaved chunks of
+// kChunk consecutive C blocks.  One LDS stage per wave: a product is written
+// to the stage after the previous one has been read.
+__global__ __launch_bounds__(256, 2) void k_numeric_split23(
+    const uint16_t* __restrict__ As, const uint16_t* __restrict__ Bs, const double* __restrict__ Ov,
+    const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
+    const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals,
+    int use_old, double alpha, double beta) {
+  constexpr int NE = kE * kE;
+  constexpr int PER_C = (NE + 63) / 64;
+  constexpr int LAST_C = NE - 64 * (PER_C - 1);
+  __shared__ __align__(16) unsigned char lds[4][kLdsStage];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned char* stage = &lds[wv][0];
+  for (int x = lane; x < kLdsStage / 16; x += 64) reinterpret_cast<uint4*>(stage)[x] = make_uint4(0, 0, 0, 0);
+
+  // LDS byte offset of chunk u*64 + lane of a stored split block
+  int off[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int c = (u < kPer - 1 || lane < kLast) ? lane + 64 * u : 0;
+    const int s = c / kChunksPerSlice, w = c - s * kChunksPerSlice;
+    off[u] = s * kLdsSlice + (w / 3) * kLdsRow + (w % 3) * 16;
+  }
+  const bool tail = lane < kLast;
+  // MFMA operand address (bytes) of this lane within a slice, tile row/col 0
+  const int opnd = (lane & 15) * kLdsRow + (lane >> 4) * 16;
+
+  const int32_t nnzc = live_nnzc(totals);
+  if (nnzc == 0) return;
+  constexpr int kXcds = 8, kChunk = 8;
+  const int32_t xcd = blockIdx.x % kXcds;
+  const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
+  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
+  const int64_t P = prod_ptr[nnzc];
+  const int32_t X0 = lower_bound_cs(prod_ptr, nnzc, P * xcd / kXcds);
+  const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_cs(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
+
+  int32_t iq = wix;
+  int64_t ip = 0, ip_end = 0;
+  if (X0 + (int64_t)iq * kChunk < X1) {
+    const int32_t c0 = X0 + iq * kChunk;
+    ip = prod_ptr[c0];
+    ip_end = prod_ptr[min(c0 + kChunk, X1)];
+  }
+  auto next_index = [&]() -> int64_t {
+    while (ip >= ip_end) {
+      iq += wpx;
+      if (X0 + (int64_t)iq * kChunk >= X1) return -1;
+      const int32_t c0 = X0 + iq * kChunk;
+      ip = prod_ptr[c0];
+      ip_end = prod_ptr[min(c0 + kChunk, X1)];
+    }
+    return ip++;
+  };
+  int32_t qa0 = -1, qb0 = -1, qa1 = -1, qb1 = -1;
+  {
+    const int64_t n0 = next_index();
+    if (n0 >= 0) {
+      qa0 = prod_a[n0];
+      qb0 = prod_b[n0];
+    }
+    const int64_t n1 = next_index();
+    if (n1 >= 0) {
+      qa1 = prod_a[n1];
+      qb1 = prod_b[n1];
+    }
+  }
+  uint4 opa[kPer], opb[kPer];
+  auto fetch_next = [&]() {
+    if (qa0 >= 0) {
+      const uint4* Ab = reinterpret_cast<const uint4*>(As + (int64_t)qa0 * kSplitBlock) + lane;
+      const uint4* Bb = reinterpret_cast<const uint4*>(Bs + (int64_t)qb0 * kSplitBlock) + lane;
+#pragma unroll
+      for (int u = 0; u < kPer - 1; ++u) {
+        opa[u] = Ab[64 * u];
+        opb[u] = Bb[64 * u];
+      }
+      opa[kPer - 1] = tail ? Ab[64 * (kPer - 1)] : make_uint4(0, 0, 0, 0);
+      opb[kPer - 1] = tail ? Bb[64 * (kPer - 1)] : make_uint4(0, 0, 0, 0);
+    }
+    qa0 = qa1;
+    qb0 = qb1;
+    const int64_t n = next_index();
+    qa1 = n >= 0 ? prod_a[n] : -1;
+    qb1 = n >= 0 ? prod_b[n] : -1;
+  };
+  auto stage_write = [&]() {
+#pragma unroll
+    for (int u = 0; u < kPer - 1; ++u) {
+      *reinterpret_cast<uint4*>(stage + off[u]) = opa[u];
+      *reinterpret_cast<uint4*>(stage + kLdsOperand + off[u]) = opb[u];
+    }
+    if (tail) {
+      *reinterpret_cast<uint4*>(stage + off[kPer - 1]) = opa[kPer - 1];
+      *reinterpret_cast<uint4*>(stage + kLdsOperand + off[kPer - 1]) = opb[kPer - 1];
+    }
+  };
+
+  double acc[16];  // C tile (mt, nt) item i at acc[4*(2*mt+nt) + i]
+  auto multiply_stage = [&]() {
+    bf16x8 a[3][2], b[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[s][t] = *reinterpret_cast<const bf16x8*>(stage + s * kLdsSlice + t * 16 * kLdsRow + opnd);
+        b[s][t] = *reinterpret_cast<const bf16x8*>(stage + kLdsOperand + s * kLdsSlice + t * 16 * kLdsRow + opnd);
+      }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        // term products, smallest first: (0,2) (1,1) (2,0) (0,1) (1,0) (0,0)
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][mt], b[2][nt], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][mt], b[1][nt], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][mt], b[0][nt], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][mt], b[1][nt], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][mt], b[0][nt], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][mt], b[0][nt], c, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[4 * (2 * mt + nt) + i] += (double)c[i];
+      }
+  };
+
+  int32_t cq = wix, c = 0, c1 = 0;
+  int64_t p = 0, pe = 0;
+  if (X0 + (int64_t)cq * kChunk >= X1) return;
+  c = X0 + cq * kChunk;
+  c1 = min(c + kChunk, X1);
+  p = prod_ptr[c];
+  pe = prod_ptr[c + 1];
+#pragma unroll
+  for (int x = 0; x < 16; ++x) acc[x] = 0.0;
+
+  // Finish every C block that ends at p: park alpha*acc in the stage (free:
+  // the next product is written afterwards), add beta*C_in, store coalesced.
+  auto advance = [&]() -> bool {
+    double* const tile = reinterpret_cast<double*>(stage);
+    const bool tl = lane < LAST_C;
+    while (p == pe) {
+      wsync();
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int R = 16 * mt + 4 * (lane >> 4) + i, Cc = 16 * nt + (lane & 15);
+            if (R < kE && Cc < kE) tile[R * kE + Cc] = alpha * acc[4 * (2 * mt + nt) + i];
+          }
+      wsync();
+      const int32_t o = use_old ? c_old_idx[c] : -1;
+      double* out = Cv + (int64_t)c * NE + lane;
+      const double* tp = tile + lane;
+      if (o >= 0) {
+        const double* ov = Ov + (int64_t)o * NE + lane;
+        double ol[PER_C];
+#pragma unroll
+        for (int u = 0; u < PER_C - 1; ++u) ol[u] = ov[64 * u];
+        ol[PER_C - 1] = tl ? ov[64 * (PER_C - 1)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PER_C - 1; ++u) out[64 * u] = tp[64 * u] + beta * ol[u];
+        if (tl) out[64 * (PER_C - 1)] = tp[64 * (PER_C - 1)] + beta * ol[PER_C - 1];
+      } else {
+#pragma unroll
+        for (int u = 0; u < PER_C - 1; ++u) out[64 * u] = tp[64 * u];
+        if (tl) out[64 * (PER_C - 1)] = tp[64 * (PER_C - 1)];
+      }
+      wsync();
+      // the parked tile overwrote stage bytes that must read as zero padding
+      for (int x = lane; x < (NE * 8 + 15) / 16; x += 64)
+        reinterpret_cast<uint4*>(stage)[x] = make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[x] = 0.0;
+      ++c;
+      if (c == c1) {
+        cq += wpx;
+        if (X0 + (int64_t)cq * kChunk >= X1) return false;
+        c = X0 + cq * kChunk;
+        c1 = min(c + kChunk, X1);
+        p = prod_ptr[c];
+      }
+      pe = prod_ptr[c + 1];
+    }
+    return true;
+  };
+
+  // Pipeline: product n is fetched at step n-1, written at the start of step
+  // n (after the previous product has been read) and multiplied.
+  if (qa0 >= 0) fetch_next();
+  for (;;) {
+    if (p == pe && !advance()) break;
+    wsync();
+    stage_write();
+    fetch_next();
+    wsync();
+    multiply_stage();
+    ++p;
+  }
+}
+
+}  // namespace
+
+int64_t split_elems(int64_t nblocks) { return nblocks * kSplitBlock; }
+
+hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int64_t bound, int transpose,
+                               uint16_t* out, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
+  int64_t blocks = (bound * kSlice + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_split_bf16x3, dim3((uint32_t)blocks), dim3(256), 0, s, values, d_nnzb, transpose, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, hipStream_t s) {
+  if (a.nnzc_bound <= 0) return hipSuccess;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int32_t blocks = ((cus * 2 + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_numeric_split23, dim3(blocks), dim3(256), 0, s, As, Bs,
+                     a.use_old ? a.Cin.values : a.c_values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
+                     a.c_values, a.totals, a.use_old, a.alpha, a.beta);
+  return hipGetLastError();
+}
+
+}  // namespace bsmm

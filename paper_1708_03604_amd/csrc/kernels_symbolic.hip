@@ -315,6 +315,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
   __shared__ int32_t s_ne;
   const int tid = threadIdx.x;
   constexpr int kPer = kMaxRowBlocks / kSymThreads;
+  if (g.totals[kTotAbort]) return;
   for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
     for (int h = tid; h < kHashSlots; h += kSymThreads) {
       hkey[h] = -1;
@@ -421,14 +422,26 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
       for (int32_t p = fill_entry_of(ra, nA, t0); p < nA && ra.pre[p] < t1; ++p) {
         const int32_t u0 = ra.pre[p] > t0 ? ra.pre[p] : t0;
         const int32_t u1 = ra.pre[p + 1] < t1 ? ra.pre[p + 1] : t1;
+        int64_t aoff = 0;
+        int32_t k = 0;
+        if (g.desc && u0 < u1) {
+          aoff = g.A.blk_off[a0 + p];
+          k = (int32_t)((g.A.blk_off[a0 + p + 1] - aoff) / g.c_row_sizes[i]);
+        }
         for (int32_t t = u0 + tid; t < u1; t += kSymThreads) {
           const int h = cslot[t - t0];
           if (h >= 0) {
             const int r = hcnt[h];
             const int32_t pos = spre[r] + cursor[r];
             cursor[r] = cursor[r] + 1;
+            const int32_t q = ra.qs[p] + (t - ra.pre[p]);
             g.prod_a[prow + pos] = a0 + p;
-            g.prod_b[prow + pos] = ra.qs[p] + (t - ra.pre[p]);
+            g.prod_b[prow + pos] = q;
+            if (g.desc) {
+              const int64_t boff = g.B.blk_off[q];
+              g.desc[prow + pos] = make_int4((int32_t)(uint32_t)aoff, (int32_t)((uint32_t)(aoff >> 32) | ((uint32_t)k << 24)),
+                                             (int32_t)(uint32_t)boff, (int32_t)(uint32_t)(boff >> 32));
+            }
           }
         }
         __syncthreads();
@@ -457,7 +470,9 @@ __global__ __launch_bounds__(256) void k_finish_rows(int32_t nbrows, const int64
                                                      const int64_t* __restrict__ np_pre,
                                                      const int64_t* __restrict__ nv_pre,
                                                      int32_t* __restrict__ c_row_ptr, int64_t* __restrict__ prod_ptr,
-                                                     int64_t* __restrict__ c_blk_off) {
+                                                     int64_t* __restrict__ c_blk_off,
+                                                     const int64_t* __restrict__ totals) {
+  if (totals[kTotAbort]) return;
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i <= nbrows) c_row_ptr[i] = (int32_t)nc_pre[i];
   if (i == 0) {
@@ -468,13 +483,14 @@ __global__ __launch_bounds__(256) void k_finish_rows(int32_t nbrows, const int64
 }
 
 hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
-                              int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, hipStream_t s) {
+                              int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, const int64_t* totals,
+                              hipStream_t s) {
   hipLaunchKernelGGL(k_finish_rows, dim3((nbrows + 1 + 255) / 256), dim3(256), 0, s, nbrows, nc_pre, np_pre, nv_pre,
-                     c_row_ptr, prod_ptr, c_blk_off);
+                     c_row_ptr, prod_ptr, c_blk_off, totals);
   return hipGetLastError();
 }
 
-// totals[0..3] = last entries of the four prefixes; totals[4] = flags.
+// totals[0..5] = totals of the per-row counts and the flags (see kTot*).
 __global__ void k_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
                                 const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
                                 int64_t* totals) {
@@ -485,6 +501,7 @@ __global__ void k_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t*
     totals[3] = cand_pre[n];
     totals[4] = (int64_t)*flags;
     totals[5] = nf_pre[n];
+    totals[kTotAbort] = 0;
   }
 }
 

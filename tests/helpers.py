@@ -90,3 +90,18 @@ def brute_products(A, B, nA=None, nB=None, eps=0.0):
                     continue
                 out.append((i, k, B.col_idx[q], p, q))
     return out
+
+
+def oracle_sign_chain(X0, steps, eps):
+    """The Newton-Schulz sequence of the chain driver, run with the oracle:
+    T = 3I - X X (on-the-fly filter eps, then filter eps), X <- 1/2 X T
+    (same), then R = X X - I and ||R||_F.  Returns (X, ||R||_F)."""
+    import oracle
+    from paper_1708_03604_amd.workloads import identity_like
+    I3, I1 = identity_like(X0, 3.0), identity_like(X0, 1.0)
+    X = X0
+    for _ in range(steps):
+        T = oracle.filter(oracle.multiply(-1.0, X, X, 1.0, I3, eps), eps)
+        X = oracle.filter(oracle.multiply(0.5, X, T, 0.0, None, eps), eps)
+    R = oracle.multiply(1.0, X, X, -1.0, I1, 0.0)
+    return X, oracle.frobenius(R)

@@ -71,6 +71,8 @@ SIZE_SETS = {
     "mixed_small": ([1, 2, 3, 7] * 5, [4, 1, 9] * 6, [2, 2, 1, 11] * 4),
     "b6": ([6] * 30, [6] * 30, [6] * 30),
     "b32": ([32] * 10, [32] * 10, [32] * 10),
+    # every class boundary of the small-block path: edges 1, 8, 9, 15, 16
+    "edge16": ([16, 9, 8, 1, 15] * 5, [16, 8, 3, 16, 9] * 6, [9, 16, 8, 2] * 6),
 }
 
 

@@ -1,0 +1,175 @@
+"""Reserved (device-sized, graph-capturable) operation, the device Frobenius
+norm and the Newton-Schulz chain, through the C-ABI.
+
+A reserved multiply or filter must give bit-for-bit the same pattern, stack
+and values as the synchronous call (same kernels, sizes read on the device);
+the chain is compared with the same sequence run by the oracle (pattern
+exact, values within the FP64 tolerance), and every replay of the captured
+graph must reproduce the eager chain bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_sign_chain
+from paper_1708_03604_amd import bsmm
+from paper_1708_03604_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+def rel_err(got, ref):
+    d = np.linalg.norm(got - ref)
+    n = np.linalg.norm(ref)
+    return d / n if n > 0 else d
+
+
+def run(A, B, Co, alpha, beta, eps, reserve=None, in_place=False):
+    dA = bsmm.Matrix.from_csr(A)
+    dB = bsmm.Matrix.from_csr(B)
+    if in_place:
+        dC = bsmm.Matrix.from_csr(Co)
+        dCin = dC
+    else:
+        dCin = bsmm.Matrix.from_csr(Co) if Co is not None else None
+        dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
+    if reserve:
+        bsmm.bsmm_reserve(dC.handle, *reserve)
+    bsmm.multiply(alpha, dA, dB, beta, dCin, dC, eps)
+    out = dC.to_host() + (dC.stack(), bsmm.bsmm_stats(dC.handle))
+    for m in {id(x): x for x in (dA, dB, dCin, dC) if x is not None}.values():
+        m.close()
+    return out
+
+
+CASES = {
+    "b23": ([23] * 16, [23] * 16, [23] * 16),
+    "b5_13": ([5, 13, 13, 5, 5, 13] * 4, [13, 5, 5, 13] * 5, [5, 13, 5] * 7),
+    "b32": ([32] * 8, [32] * 8, [32] * 8),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("in_place", [False, True])
+def test_reserved_equals_synchronous(name, in_place):
+    rs, ks, cs = CASES[name]
+    A = W.random_matrix(101, rs, ks, 0.35)
+    B = W.random_matrix(102, ks, cs, 0.35)
+    Co = W.random_matrix(103, rs, cs, 0.3)
+    eps = 0.5
+    ref = run(A, B, Co, 1.5, -0.5, eps, in_place=in_place)
+    caps = (len(rs) * len(cs), int(np.sum(rs)) * int(np.sum(cs)), len(rs) * len(ks) * len(cs))
+    got = run(A, B, Co, 1.5, -0.5, eps, reserve=caps, in_place=in_place)
+    for r, g in zip(ref[:4], got[:4]):
+        assert np.array_equal(r, g)
+    assert ref[4] == got[4]
+
+
+def test_reserved_overflow_is_reported_and_recoverable():
+    sizes = [23] * 12
+    A = W.random_matrix(111, sizes, sizes, 0.5)
+    dA = bsmm.Matrix.from_csr(A)
+    dC = bsmm.Matrix.empty(sizes, sizes)
+    bsmm.bsmm_reserve(dC.handle, 2, 2 * 529, 4)
+    bsmm.multiply(1.0, dA, dA, 0.0, None, dC, 0.0)  # does not fit: nothing written
+    with pytest.raises(bsmm.BsmmError) as e:
+        dC.info()
+    assert e.value.status == "BSMM_E_CAPACITY"
+    assert dC.info()[2] == 0  # emptied, and usable again
+    bsmm.bsmm_reserve(dC.handle, 144, 144 * 529, 12 ** 3)
+    bsmm.multiply(1.0, dA, dA, 0.0, None, dC, 0.0)
+    ref = oracle.multiply(1.0, A, A, 0.0, None, 0.0)
+    rp, ci, v = dC.to_host()
+    assert np.array_equal(ci, ref.col_idx)
+    assert rel_err(v, ref.values) <= REL_TOL
+    dA.close()
+    dC.close()
+
+
+def test_reserved_filter_equals_synchronous():
+    sizes = [5, 13, 23] * 5
+    M = W.random_matrix(121, sizes, sizes, 0.5)
+    eps = float(np.median(oracle.norms(M)))
+    a = bsmm.Matrix.from_csr(M)
+    b = bsmm.Matrix.from_csr(M)
+    bsmm.bsmm_reserve(b.handle, M.nnzb, M.nvals, 1)
+    bsmm.bsmm_filter(a.handle, eps)
+    bsmm.bsmm_filter(b.handle, eps)
+    for x, y in zip(a.to_host(), b.to_host()):
+        assert np.array_equal(x, y)
+    ref = oracle.filter(M, eps)
+    assert np.array_equal(a.to_host()[1], ref.col_idx)
+    a.close()
+    b.close()
+
+
+def test_frobenius_matches_oracle():
+    import torch
+    sizes = [5, 13, 23, 1, 64] * 6
+    M = W.random_matrix(131, sizes, sizes, 0.4)
+    d = bsmm.Matrix.from_csr(M)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    bsmm.bsmm_frobenius(d.handle, out)
+    got = float(out.cpu()[0])
+    ref = oracle.frobenius(M)
+    assert abs(got - ref) <= 1e-14 * ref
+    d.close()
+
+
+def _chain_input(nmol=24, seed=5000):
+    X0, _ = W.symmetric_scaled(seed=seed, nmol=nmol)
+    return X0
+
+
+def test_chain_eager_matches_oracle():
+    from paper_1708_03604_amd.chain import SignChain
+    X0 = _chain_input()
+    steps, eps = 12, 1e-7
+    ch = SignChain(X0, steps=steps, eps=eps)
+    ch.enqueue()
+    ch.stream.synchronize()
+    rp, ci, v = ch.final.to_host()
+    res = float(ch.residual.cpu()[0])
+    Xr, res_ref = oracle_sign_chain(X0, steps, eps)
+    assert np.array_equal(rp, Xr.row_ptr)
+    assert np.array_equal(ci, Xr.col_idx)
+    assert rel_err(v, Xr.values) <= 1e-11
+    assert abs(res - res_ref) <= 1e-10 * max(res_ref, 1e-300)
+    ch.close()
+
+
+def test_chain_graph_replays_match_eager():
+    import torch
+    from paper_1708_03604_amd.chain import SignChain
+    X0 = _chain_input(nmol=16, seed=5100)
+    ch = SignChain(X0, steps=6, eps=1e-7)
+    ch.enqueue()
+    ch.stream.synchronize()
+    ref = ch.final.to_host()
+    ref_res = float(ch.residual.cpu()[0])
+    ch.capture()
+    for rep in range(3):
+        ch.residual.zero_()
+        torch.cuda.synchronize()
+        ch.replay()
+        ch.stream.synchronize()
+        got = ch.final.to_host()
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y), f"replay {rep}"
+        assert float(ch.residual.cpu()[0]) == ref_res
+        # unrelated eager work between replays
+        a = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (a @ a).sum().item()
+    ch.close()
