@@ -112,7 +112,7 @@ struct bsmm_matrix {
   DBuf<int4> class_list;          // C blocks by padded shape class (small-block path), 2 per block
   DBuf<int4> prod_desc;           // per product operand offsets (small-block path)
   DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
-  DBuf<int64_t> class_cnt, class_pre;
+  DBuf<int64_t> class_cnt, class_pre, class_np, class_q;
   DBuf<int32_t> class_start;
   int64_t* h_totals = nullptr;  // pinned, kPinned entries
   // phase timing: 7 events per recorded multiply
@@ -353,6 +353,8 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->split_a.release();
   m->split_b.release();
   m->class_cnt.release();
+  m->class_np.release();
+  m->class_q.release();
   m->class_pre.release();
   m->class_start.release();
   m->dsz.release();
@@ -622,12 +624,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       return fail(BSMM_E_NOMEM, "device allocation for the split operands failed");
   }
   if (small) {
-    const int64_t ncl = class_list_tmp_elems(nnzc_bound);
+    const int64_t ncl = class_list_tmp_elems(nnzc_bound), nce = class_entries(nnzc_bound);
     if (C->class_list.ensure(2 * std::max<int64_t>(nnzc_bound, 1)) != hipSuccess ||
         C->prod_desc.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
         C->class_cnt.ensure(ncl) != hipSuccess || C->class_pre.ensure(ncl) != hipSuccess ||
+        C->class_np.ensure(std::max<int64_t>(nce, 1)) != hipSuccess || C->class_q.ensure(nce + 1) != hipSuccess ||
         C->class_start.ensure(5) != hipSuccess ||
-        C->scan_tmp.ensure(std::max(scan_tmp_elems(nbrows), scan_tmp_elems(ncl)) + 2) != hipSuccess)
+        C->scan_tmp.ensure(std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(nce)}) + 2) !=
+            hipSuccess)
       return fail(BSMM_E_NOMEM, "device allocation for the block classes failed");
   }
   // a reallocation above may have freed C_in's storage only if C_in == C and
@@ -645,7 +649,6 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.c_old_idx = C->old_idx.p;
   g.prod_a = C->prod_a.p;
   g.prod_b = C->prod_b.p;
-  g.desc = small ? C->prod_desc.p : nullptr;
   HIP_TRY(launch_sym_fill(g, s));
   mark(C, ev, 4, s);
 
@@ -673,8 +676,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     HIP_TRY(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
   } else if (small) {
     HIP_TRY(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
-                               C->class_start.p, s));
-    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->prod_desc.p, s));
+                               C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
+    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, s));
   } else {
     HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
   }
@@ -762,13 +765,14 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
     m->cur.release();
     m->cur = fresh;
   }
-  const int64_t ncl = class_list_tmp_elems(cb);
-  const int64_t tmp = std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(cb)}) + 2;
+  const int64_t ncl = class_list_tmp_elems(cb), nce = class_entries(cb);
+  const int64_t tmp = std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(cb), scan_tmp_elems(nce)}) + 2;
   bool ok = ensure_storage(m->spare, nbrows, cb, cv) == hipSuccess && m->prod_ptr.ensure(cb + 1) == hipSuccess &&
             m->prod_a.ensure(cp) == hipSuccess && m->prod_b.ensure(cp) == hipSuccess &&
             m->old_idx.ensure(cb) == hipSuccess && m->prod_desc.ensure(cp) == hipSuccess &&
             m->class_list.ensure(2 * cb) == hipSuccess && m->class_cnt.ensure(ncl) == hipSuccess &&
             m->class_pre.ensure(ncl) == hipSuccess && m->class_start.ensure(5) == hipSuccess &&
+            m->class_np.ensure(nce) == hipSuccess && m->class_q.ensure(nce + 1) == hipSuccess &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
             m->flags.ensure(1) == hipSuccess && m->work.ensure(1) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&

@@ -81,8 +81,6 @@ struct SymArgs {
   int32_t* c_old_idx;   // [nnzc] block of C_in or -1
   int32_t* prod_a;      // [nprod]
   int32_t* prod_b;      // [nprod]
-  // optional (small-block path): per product {A value offset | k << 56, B value offset}
-  int4* desc;
   const int64_t* totals;  // per-multiply totals (the fill does nothing once aborted)
 };
 
@@ -142,11 +140,15 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
 constexpr int kSmallEdge = 16;
 int64_t class_list_tmp_elems(int64_t nnzc_bound);  // entries of cnt and cnt_pre
 // list holds two int4 per C block: {m | n << 8, first product, product count, 0}
-// and {C value offset, C_in value offset or -1} (int64 pairs).
+// and {C value offset, C_in value offset or -1} (int64 pairs).  cnp and qstart
+// hold class_entries(bound) (+1) int64: product counts in list order and their
+// exclusive scan; desc receives the operand descriptors {A value offset |
+// k << 56, B value offset} of every product in list order.
+int64_t class_entries(int64_t nnzc_bound);
 hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, int64_t* tmp, int4* list,
-                              int32_t* cls_start, hipStream_t s);
-hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int4* desc,
-                                hipStream_t s);
+                              int32_t* cls_start, int64_t* cnp, int64_t* qstart, int4* desc, hipStream_t s);
+hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int64_t* qstart,
+                                const int4* desc, hipStream_t s);
 
 // Split precision (23x23 blocks): FP64 values -> three BF16 terms per value,
 // split_elems(nblocks) uint16 per matrix; transpose = 1 stores each block

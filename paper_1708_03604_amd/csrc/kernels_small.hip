@@ -14,14 +14,13 @@
 // At the end of a C block the four K slices are summed with cross-lane swaps.
 //
 // Operands.  A product's A block (m x k, row-major) and B block (k x n) are
-// contiguous in memory; the wave loads them as one run of m*k + k*n doubles
-// (lane l takes elements l, l+64, ...), so every load is coalesced whatever
-// the sizes.  Products are fetched D steps before they are multiplied (D
-// register slots) and written one step ahead into one of two LDS stages: A
-// transposed (row t holds A(:, t)) and B as is, both with a row stride of 18
-// doubles, so a lane reads its RM rows and RN columns of inner index t with
-// 16-byte loads.  Padding rows and columns are never zeroed: a padded row or
-// column of A or B only reaches padded outputs, which are never stored.
+// each contiguous in memory; the wave loads them with lane l taking elements
+// l, l+64, ..., so every load is coalesced whatever the sizes.  Products are
+// fetched D steps before they are multiplied (D register slots) and copied
+// one step ahead, exactly as stored, into one of two LDS stages (contiguous
+// writes, free of bank conflicts).  A lane then reads A(r, t) and B(t, c) for
+// its RM rows and RN columns with 8-byte loads.  Padding rows and columns are
+// never zeroed: they only reach padded outputs, which are never stored.
 #include <type_traits>
 
 #include "bsmm_internal.h"
@@ -44,6 +43,32 @@ __device__ __forceinline__ void static_for(F&& f) {
 constexpr int kClassThreads = 256;
 constexpr int kClassPer = 8;
 constexpr int kClassChunk = kClassThreads * kClassPer;  // C blocks per workgroup
+
+// Schedule of the numeric kernel, shared with the list layout: each class
+// list is cut into 8 XCD parts (part x runs on XCD x); a part's C blocks are
+// dealt to its wpx waves in chunks of kChunk consecutive blocks, round robin,
+// so at any time an XCD works on a few consecutive block rows (their A blocks
+// stay in its L2).  The list is stored so that each wave's chunks are
+// contiguous: a wave then reads its entries and descriptors sequentially.
+constexpr int kXcds = 8;
+constexpr int kChunk = 16;
+
+// First stored position (within a part of n entries) of wave w's entries.
+__device__ __forceinline__ int64_t wave_base(int64_t n, int32_t wpx, int32_t w) {
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  const int64_t chunks = (nch / wpx) * w + min<int64_t>(nch % wpx, w);
+  int64_t e = chunks * kChunk;
+  const int64_t last = nch - 1;  // the only chunk that may be short
+  if (nch > 0 && (last % wpx) < w) e -= nch * kChunk - n;
+  return e;
+}
+
+// Stored position of the t-th entry (natural order) of a part of n entries.
+__device__ __forceinline__ int64_t stored_pos(int64_t t, int64_t n, int32_t wpx) {
+  const int64_t c = t / kChunk, u = t - c * kChunk;
+  const int32_t w = (int32_t)(c % wpx);
+  return wave_base(n, wpx, w) + (c / wpx) * kChunk + u;
+}
 
 __device__ __forceinline__ int shape_class(const int32_t* __restrict__ c_col_idx,
                                            const int32_t* __restrict__ c_col_sizes,
@@ -107,7 +132,8 @@ __global__ __launch_bounds__(kClassThreads) void k_class_scatter(
     const int64_t* __restrict__ totals, int32_t nchunks, const int32_t* __restrict__ c_col_idx, const int32_t* __restrict__ c_col_sizes,
     const int64_t* __restrict__ c_blk_off, const int64_t* __restrict__ prod_ptr,
     const int32_t* __restrict__ c_old_idx, const int64_t* __restrict__ old_off, int use_old,
-    const int64_t* __restrict__ off, int4* __restrict__ list, int32_t* __restrict__ cls_start) {
+    const int64_t* __restrict__ off, int4* __restrict__ list, int32_t* __restrict__ cls_start,
+    int64_t* __restrict__ cnp, int32_t wpx) {
   const int32_t nnzc = live_nnzc(totals);
   const int32_t chunk = blockIdx.x;
   int cls[kClassPer];
@@ -128,27 +154,71 @@ __global__ __launch_bounds__(kClassThreads) void k_class_scatter(
   for (int u = 0; u < kClassPer; ++u) {
     if (cls[u] >= 0) {
       const int32_t c = chunk * kClassChunk + threadIdx.x * kClassPer + u;
-      const int64_t pos = off[(int64_t)cls[u] * nchunks + chunk] + (int64_t)((run >> (16 * cls[u])) & 0xffff);
+      const int64_t nat = off[(int64_t)cls[u] * nchunks + chunk] + (int64_t)((run >> (16 * cls[u])) & 0xffff);
+      // natural position -> stored position (see stored_pos)
+      const int64_t L0 = off[(int64_t)cls[u] * nchunks], L = off[(int64_t)(cls[u] + 1) * nchunks] - L0;
+      const int64_t t = nat - L0;
+      int x = 0;
+      while (x < kXcds - 1 && L * (x + 1) / kXcds <= t) ++x;
+      const int64_t p0x = L * x / kXcds, nx = L * (x + 1) / kXcds - p0x;
+      const int64_t pos = L0 + p0x + stored_pos(t - p0x, nx, wpx);
       const int64_t p0 = prod_ptr[c];
       const int32_t o = use_old ? c_old_idx[c] : -1;
       const int64_t coff = c_blk_off[c];
       const int64_t ooff = o >= 0 ? old_off[o] : -1;
-      list[2 * pos] = make_int4(mn[u], (int32_t)p0, (int32_t)(prod_ptr[c + 1] - p0), 0);
+      const int32_t np = (int32_t)(prod_ptr[c + 1] - p0);
+      list[2 * pos] = make_int4(mn[u], (int32_t)p0, np, 0);
+      cnp[pos] = np;
       list[2 * pos + 1] = make_int4((int32_t)(uint32_t)coff, (int32_t)(uint32_t)((uint64_t)coff >> 32),
                                     (int32_t)(uint32_t)ooff, (int32_t)(uint32_t)((uint64_t)ooff >> 32));
       run += 1ull << (16 * cls[u]);
     }
   }
+  // positions past the live result (reserved capacity) count no products
+#pragma unroll
+  for (int u = 0; u < kClassPer; ++u) {
+    const int32_t c = chunk * kClassChunk + threadIdx.x * kClassPer + u;
+    if (c >= nnzc && c < nchunks * kClassChunk) cnp[c] = 0;
+  }
   if (chunk == 0 && threadIdx.x <= 4) cls_start[threadIdx.x] = (int32_t)off[(int64_t)threadIdx.x * nchunks];
+}
+
+// Product descriptors in list order: for list entry e (a C block with np
+// products from stack position p0), desc[qstart[e] + l] = {A value offset
+// | k << 56, B value offset} of its l-th product.  A wave serves four
+// entries at a time, 16 lanes each (a C block has about a dozen products).
+__global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ totals,
+                                                    const int4* __restrict__ list,
+                                                    const int64_t* __restrict__ qstart,
+                                                    const int32_t* __restrict__ prod_a,
+                                                    const int32_t* __restrict__ prod_b,
+                                                    const int64_t* __restrict__ Aoff,
+                                                    const int64_t* __restrict__ Boff, int4* __restrict__ desc) {
+  const int32_t nnzc = live_nnzc(totals);
+  const int lane = threadIdx.x & 63, g = lane >> 4, l0 = lane & 15;
+  const int32_t nwaves = gridDim.x * 4;
+  for (int32_t e0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4; e0 < nnzc; e0 += nwaves * 4) {
+    const int32_t e = e0 + g;
+    if (e >= nnzc) continue;
+    const int4 ent = list[2 * (int64_t)e];
+    const int32_t m = ent.x & 255;
+    const int64_t q = qstart[e];
+    for (int32_t l = l0; l < ent.z; l += 16) {
+      const int64_t p = (int64_t)ent.y + l;
+      const int32_t a = prod_a[p], b = prod_b[p];
+      const int64_t ao = Aoff[a];
+      const int32_t k = (int32_t)((Aoff[a + 1] - ao) / m);
+      const int64_t bo = Boff[b];
+      desc[q + l] = make_int4((int32_t)(uint32_t)ao, (int32_t)((uint32_t)(ao >> 32) | ((uint32_t)k << 24)),
+                              (int32_t)(uint32_t)bo, (int32_t)(uint32_t)(bo >> 32));
+    }
+  }
 }
 
 // ------------------------------------------------------------ numeric
 
-constexpr int kStride = 18;                  // doubles per LDS row
-constexpr int kOperand = 16 * kStride;       // one staged operand (16 inner rows)
-constexpr int kStage = 2 * kOperand;         // A^T then B
-constexpr int kXcds = 8;
-constexpr int kChunk = 16;                   // C blocks per scheduling chunk (<= 64)
+constexpr int kOperand = 256;  // doubles of one staged operand (a block of at most 16 x 16)
+constexpr int kStage = 2 * kOperand;  // A then B, each stored exactly as in memory
 
 __device__ __forceinline__ void swap32(double& lo, double& hi) {
   // lanes 0-31 end with (lo, partner lo), lanes 32-63 with (partner hi, hi)
@@ -179,10 +249,20 @@ struct SmallOps {
   const double* Bv;
   const double* Ov;
   const int4* list;
+  const int64_t* qstart;
   const int4* desc;
   double* Cv;
   double alpha, beta;
 };
+
+// Take ownership of a batch that was loaded a batch earlier: the empty asm
+// reads the registers, so the compiler waits for their load here, once per
+// batch; afterwards they are plain values and the per-product readlanes need
+// no wait (the wait count the compiler would otherwise derive at each
+// readlane assumes the batch load may be the most recent one).
+__device__ __forceinline__ void settle(int4& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
 
 __device__ __forceinline__ int64_t make64(int32_t lo, int32_t hi) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
@@ -190,60 +270,90 @@ __device__ __forceinline__ int64_t make64(int32_t lo, int32_t hi) {
 
 // One class: C blocks list[L0, L1) padded to MP x NP, D products in flight.
 //
-// The wave walks its C blocks (chunks of kChunk list entries) as one stream of
-// slots: one slot per product, and one empty slot for a C block without
-// products.  A slot carries the operand loads of its product and, on the last
-// slot of a C block, the block's finishing data.  Every slot issues exactly
-// ROWS vector loads (lanes past the product's elements reread its first
-// element), so the compiler can count outstanding loads exactly and the D
-// slots in flight never force each other to complete early.  Indices come
-// from scalar loads of the list entry and of the product descriptor, both
-// read in sequential order.
+// Each wave takes a contiguous run of the class list (its XCD's part of the
+// list split evenly over the XCD's waves), so both its list entries and its
+// product descriptors (stored in list order) are contiguous.  The wave walks
+// them as one stream of slots: one slot per product, and one empty slot for a
+// C block without products.  A slot carries the operand loads of its product
+// and, on the last slot of a C block, the block's finishing data.
+//
+// Loads are arranged so that no wait ever stalls on a recent load: every
+// slot issues exactly RA + RB vector loads (lanes past the product's elements
+// reread its first element), so outstanding loads are counted exactly; list
+// entries and descriptors arrive in batches of 64 (one per lane, read back
+// with readlane), each batch loaded one batch ahead; and the steady state
+// issues no scalar memory loads, whose completion every LDS wait would
+// otherwise also wait for.
 template <int MP, int NP, int D>
 __device__ __forceinline__ void small_class(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
                                             int32_t xcd, int32_t wpx, int32_t wix, int lane) {
   constexpr int RM = MP / 4, RN = NP / 4, V = RM * RN;
-  constexpr int ROWS = (MP * 16 + 16 * NP) / 64;  // element rows of the largest product (k = 16)
+  constexpr int RA = MP * 16 / 64, RB = 16 * NP / 64;  // element rows of the largest A and B blocks (k = 16)
   static_assert(V % 4 == 0 && D % 2 == 0, "tile shape");
   const int s = lane >> 4, rho = (lane >> 2) & 3, gam = lane & 3;
 
-  // This XCD's part of the list, taken in chunks of kChunk C blocks.
-  const int32_t L = L1 - L0;
-  const int32_t X0 = L0 + (int32_t)((int64_t)L * xcd / kXcds);
-  const int32_t X1 = L0 + (int32_t)((int64_t)L * (xcd + 1) / kXcds);
-  if (X0 + wix * kChunk >= X1) return;
+  // This wave's run of the list: [E0, E1), products [Q0, Q1) in list order.
+  const int64_t L = L1 - L0;
+  const int64_t X0 = L0 + L * xcd / kXcds, X1 = L0 + L * (xcd + 1) / kXcds;
+  const int32_t E0 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix));
+  const int32_t E1 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix + 1));
+  if (E0 >= E1) return;
+  const int64_t Q0 = P.qstart[E0], Q1 = P.qstart[E1];
 
-  // ---- fetch cursor: entry fe of chunk fq (entries fe .. fe_end-1), product fp
-  int32_t fq = wix, fe = X0 + wix * kChunk, fe_end = min(fe + kChunk, X1);
+  // ---- entry batches: lane u holds entry eb + u (current) and eb + 64 + u (next)
+  int32_t eb = E0, ei = E0;
+  int4 ca, cb, na, nb;
+  auto load_entries = [&](int32_t base, int4& x, int4& y) {
+    const int64_t e = base + lane < E1 ? base + lane : E1 - 1;
+    x = P.list[2 * e];
+    y = P.list[2 * e + 1];
+  };
+  load_entries(eb, ca, cb);
+  settle(ca);
+  settle(cb);
+  load_entries(eb + 64, na, nb);
+  // ---- descriptor batches: lane u holds descriptor qb + u (current) and qb + 64 + u (next)
+  int64_t qb = Q0, qi = Q0;
+  int4 cd, nd;
+  auto load_desc = [&](int64_t base, int4& x) {
+    const int64_t q = base + lane < Q1 ? base + lane : (Q1 > Q0 ? Q1 - 1 : 0);
+    x = P.desc[q];
+  };
+  load_desc(qb, cd);
+  settle(cd);
+  load_desc(qb + 64, nd);
+
+  // ---- fetch cursor: current entry (m, n, products left, finishing data)
   bool fok = true;
-  int32_t fmn = 0, fp = 0, fpe = 0;
+  int32_t fmn = 0, frem = 0;
   int64_t fcoff = 0, fooff = -1;
-  auto load_entry = [&]() {
-    const int4 a = P.list[2 * (int64_t)fe];
-    const int4 b = P.list[2 * (int64_t)fe + 1];
-    fmn = a.x;
-    fp = a.y;
-    fpe = a.y + a.z;
-    fcoff = make64(b.x, b.y);
-    fooff = make64(b.z, b.w);
+  auto take_entry = [&]() {
+    const int u = ei - eb;
+    fmn = __builtin_amdgcn_readlane(ca.x, u);
+    frem = __builtin_amdgcn_readlane(ca.z, u);
+    fcoff = make64(__builtin_amdgcn_readlane(cb.x, u), __builtin_amdgcn_readlane(cb.y, u));
+    fooff = make64(__builtin_amdgcn_readlane(cb.z, u), __builtin_amdgcn_readlane(cb.w, u));
   };
   auto next_entry = [&]() {
-    ++fe;
-    if (fe >= fe_end) {
-      fq += wpx;
-      fe = X0 + fq * kChunk;
-      if (fe >= X1) {
-        fok = false;
-        return;
-      }
-      fe_end = min(fe + kChunk, X1);
+    ++ei;
+    if (ei >= E1) {
+      fok = false;
+      return;
     }
-    load_entry();
+    if (ei - eb == 64) {
+      eb += 64;
+      ca = na;
+      cb = nb;
+      settle(ca);
+      settle(cb);
+      load_entries(eb + 64, na, nb);
+    }
+    take_entry();
   };
-  load_entry();
+  take_entry();
 
   // ---- slots: product X lives in slot X % D from its fetch to its stage write
-  double sv[D][ROWS];
+  double sa[D][RA], sb[D][RB];
   int32_t sok[D], smk[D], skn[D], sk[D], sn[D], slast[D], smn[D];
   int64_t scoff[D], sooff[D];
   auto fetch = [&](auto slot) {
@@ -253,42 +363,53 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
     sok[d] = fok;
     if (fok) {
       const int32_t m = fmn & 255, n = fmn >> 8;
-      const bool empty = fp == fpe;
       int32_t k = 0;
-      if (!empty) {
-        const int4 dsc = P.desc[fp];
-        ao = make64(dsc.x, dsc.y & 0xffffff);
-        k = (int32_t)((uint32_t)dsc.y >> 24);
-        bo = make64(dsc.z, dsc.w);
+      if (frem > 0) {
+        const int u = (int)(qi - qb);
+        const int32_t dx = __builtin_amdgcn_readlane(cd.x, u), dy = __builtin_amdgcn_readlane(cd.y, u);
+        const int32_t dz = __builtin_amdgcn_readlane(cd.z, u), dw = __builtin_amdgcn_readlane(cd.w, u);
+        ao = make64(dx, dy & 0xffffff);
+        k = (int32_t)((uint32_t)dy >> 24);
+        bo = make64(dz, dw);
         mk = m * k;
         kn = k * n;
-        ++fp;
+        --frem;
+        ++qi;
+        if (qi - qb == 64) {
+          qb += 64;
+          cd = nd;
+          settle(cd);
+          load_desc(qb + 64, nd);
+        }
       }
       smk[d] = mk;
       skn[d] = kn;
       sk[d] = k;
       sn[d] = n;
-      slast[d] = fp == fpe;
+      slast[d] = frem == 0;
       smn[d] = fmn;
       scoff[d] = fcoff;
       sooff[d] = fooff;
-      if (fp == fpe) next_entry();
+      if (frem == 0) next_entry();
     }
-    // ROWS loads, always: element e of the run A block ++ B block, or the
-    // product's first element for lanes past its end
-    const int32_t tot = mk + kn;
+    // RA + RB loads, always: lane l takes elements l, l+64, .. of the A
+    // block and of the B block, or the block's first element past its end
     const double* pa = P.Av + ao;
-    const double* pb = P.Bv + bo - mk;
+    const double* pb = P.Bv + bo;
 #pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
+    for (int j = 0; j < RA; ++j) {
       const int e = lane + 64 * j;
-      const double* src = e < mk ? pa + e : (e < tot ? pb + e : pa);
-      sv[d][j] = *src;
+      sa[d][j] = pa[e < mk ? e : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int e = lane + 64 * j;
+      sb[d][j] = pb[e < kn ? e : 0];
     }
   };
   // what each LDS stage holds: valid slot, inner size, and the finishing data
   // of its C block if the slot is the block's last
-  int32_t stok[2] = {0, 0}, stk[2] = {0, 0}, stlast[2] = {0, 0}, stmn[2] = {0, 0};
+  int32_t stok[2] = {0, 0}, stk[2] = {0, 0}, stn[2] = {0, 0}, stlast[2] = {0, 0}, stmn[2] = {0, 0};
   int64_t stcoff[2] = {0, 0}, stooff[2] = {-1, -1};
   auto stage_write = [&](auto slot, auto stage) {
     constexpr int d = decltype(slot)::value;
@@ -296,38 +417,34 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
     const int32_t mk = smk[d], kn = skn[d], k = sk[d], n = sn[d];
     stok[st] = sok[d];
     stk[st] = k;
+    stn[st] = n;
     stlast[st] = slast[d];
     stmn[st] = smn[d];
     stcoff[st] = scoff[d];
     stooff[st] = sooff[d];
     if (k == 0) return;
-    const float rk = 1.0f / (float)k, rn = 1.0f / (float)n;
-    double* At = wl + st * kStage;
-    double* Bs = At + kOperand;
-    const int32_t tot = mk + kn;
+    // A and B are copied as they are stored (row-major, dense): contiguous,
+    // bank-conflict-free writes with no index arithmetic
+    double* As = wl + st * kStage;
+    double* Bs = As + kOperand;
 #pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-      const int e = lane + 64 * j;
-      if (e < mk) {
-        const int r = (int)(((float)e + 0.5f) * rk);
-        const int t = e - r * k;
-        At[t * kStride + r] = sv[d][j];
-      } else if (e < tot) {
-        const int e2 = e - mk;
-        const int t = (int)(((float)e2 + 0.5f) * rn);
-        const int c = e2 - t * n;
-        Bs[t * kStride + c] = sv[d][j];
-      }
-    }
+    for (int j = 0; j < RA; ++j)
+      if (lane + 64 * j < mk) As[lane + 64 * j] = sa[d][j];
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+      if (lane + 64 * j < kn) Bs[lane + 64 * j] = sb[d][j];
   };
 
   double acc[V];
 #pragma unroll
   for (int x = 0; x < V; ++x) acc[x] = 0.0;
+  // Lane (s, rho, gam), inner index t: A(rho*RM + i, t) = As[(rho*RM + i)*k + t]
+  // and B(t, gam*RN + j) = Bs[t*n + gam*RN + j].  Rows and columns past the
+  // block read other staged values; they only reach padded outputs.
   auto compute = [&](auto stage) {
     constexpr int st = decltype(stage)::value;
-    const int32_t k = stk[st];
-    const double* At = wl + st * kStage + rho * RM;
+    const int32_t k = stk[st], n = stn[st];
+    const double* As = wl + st * kStage + rho * RM * k;
     const double* Bs = wl + st * kStage + kOperand + gam * RN;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -336,17 +453,9 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
         if (t < k) {
           double a[RM], b[RN];
 #pragma unroll
-          for (int h = 0; h < RM / 2; ++h) {
-            const double2 v = reinterpret_cast<const double2*>(At + t * kStride)[h];
-            a[2 * h] = v.x;
-            a[2 * h + 1] = v.y;
-          }
+          for (int i = 0; i < RM; ++i) a[i] = As[i * k + t];
 #pragma unroll
-          for (int h = 0; h < RN / 2; ++h) {
-            const double2 v = reinterpret_cast<const double2*>(Bs + t * kStride)[h];
-            b[2 * h] = v.x;
-            b[2 * h + 1] = v.y;
-          }
+          for (int jj = 0; jj < RN; ++jj) b[jj] = Bs[t * n + jj];
 #pragma unroll
           for (int i = 0; i < RM; ++i)
 #pragma unroll
@@ -443,10 +552,11 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
 __global__ __launch_bounds__(256) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
                                                        const int32_t* __restrict__ cls_start,
+                                                       const int64_t* __restrict__ qstart,
                                                        const int4* __restrict__ desc, double* __restrict__ Cv,
                                                        double alpha, double beta) {
   __shared__ __align__(16) double lds[4][2 * kStage];
-  const SmallOps P{Av, Bv, Ov, list, desc, Cv, alpha, beta};
+  const SmallOps P{Av, Bv, Ov, list, qstart, desc, Cv, alpha, beta};
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
@@ -463,13 +573,27 @@ __global__ __launch_bounds__(256) void k_numeric_small(const double* __restrict_
 
 }  // namespace
 
+// Grid of the numeric kernel: four workgroups of 4 waves per CU, a multiple
+// of the XCD count; the list layout depends on its waves per XCD.
+int32_t small_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return ((cus * 4 + kXcds - 1) / kXcds) * kXcds;
+}
+
+int32_t small_waves_per_xcd() { return small_grid() / kXcds * 4; }
+
+int64_t class_entries(int64_t nnzc_bound) {
+  return (nnzc_bound + kClassChunk - 1) / kClassChunk * kClassChunk;
+}
+
 int64_t class_list_tmp_elems(int64_t nnzc_bound) {
   const int64_t nchunks = (nnzc_bound + kClassChunk - 1) / kClassChunk;
   return 4 * nchunks + 1;
 }
 
 hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, int64_t* tmp, int4* list,
-                              int32_t* cls_start, hipStream_t s) {
+                              int32_t* cls_start, int64_t* cnp, int64_t* qstart, int4* desc, hipStream_t s) {
   const int32_t nchunks = (int32_t)((a.nnzc_bound + kClassChunk - 1) / kClassChunk);
   if (nchunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_class_count, dim3(nchunks), dim3(kClassThreads), 0, s, a.totals, nchunks, a.c_col_idx,
@@ -480,19 +604,24 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_class_scatter, dim3(nchunks), dim3(kClassThreads), 0, s, a.totals, nchunks, a.c_col_idx,
                      a.c_col_sizes, a.c_blk_off, a.prod_ptr, a.c_old_idx, a.use_old ? a.Cin.blk_off : a.c_blk_off,
-                     a.use_old, cnt_pre, list, cls_start);
+                     a.use_old, cnt_pre, list, cls_start, cnp, small_waves_per_xcd());
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(cnp, (int64_t)nchunks * kClassChunk, qstart, tmp, s);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (a.nnzc_bound + 15) / 16;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_class_desc, dim3((uint32_t)blocks), dim3(256), 0, s, a.totals, list, qstart, a.prod_a,
+                     a.prod_b, a.A.blk_off, a.B.blk_off, desc);
   return hipGetLastError();
 }
 
-hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int4* desc,
-                                hipStream_t s) {
+hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int64_t* qstart,
+                                const int4* desc, hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int32_t blocks = cus * 4;  // four workgroups of 4 waves per CU
-  blocks = ((blocks + kXcds - 1) / kXcds) * kXcds;
-  hipLaunchKernelGGL(k_numeric_small, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
-                     a.use_old ? a.Cin.values : a.c_values, list, cls_start, desc, a.c_values, a.alpha, a.beta);
+  hipLaunchKernelGGL(k_numeric_small, dim3(small_grid()), dim3(256), 0, s, a.A.values, a.B.values,
+                     a.use_old ? a.Cin.values : a.c_values, list, cls_start, qstart, desc, a.c_values, a.alpha,
+                     a.beta);
   return hipGetLastError();
 }
 

@@ -422,26 +422,14 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
       for (int32_t p = fill_entry_of(ra, nA, t0); p < nA && ra.pre[p] < t1; ++p) {
         const int32_t u0 = ra.pre[p] > t0 ? ra.pre[p] : t0;
         const int32_t u1 = ra.pre[p + 1] < t1 ? ra.pre[p + 1] : t1;
-        int64_t aoff = 0;
-        int32_t k = 0;
-        if (g.desc && u0 < u1) {
-          aoff = g.A.blk_off[a0 + p];
-          k = (int32_t)((g.A.blk_off[a0 + p + 1] - aoff) / g.c_row_sizes[i]);
-        }
         for (int32_t t = u0 + tid; t < u1; t += kSymThreads) {
           const int h = cslot[t - t0];
           if (h >= 0) {
             const int r = hcnt[h];
             const int32_t pos = spre[r] + cursor[r];
             cursor[r] = cursor[r] + 1;
-            const int32_t q = ra.qs[p] + (t - ra.pre[p]);
             g.prod_a[prow + pos] = a0 + p;
-            g.prod_b[prow + pos] = q;
-            if (g.desc) {
-              const int64_t boff = g.B.blk_off[q];
-              g.desc[prow + pos] = make_int4((int32_t)(uint32_t)aoff, (int32_t)((uint32_t)(aoff >> 32) | ((uint32_t)k << 24)),
-                                             (int32_t)(uint32_t)boff, (int32_t)(uint32_t)(boff >> 32));
-            }
+            g.prod_b[prow + pos] = ra.qs[p] + (t - ra.pre[p]);
           }
         }
         __syncthreads();
