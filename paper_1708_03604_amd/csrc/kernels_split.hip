@@ -37,6 +37,7 @@ constexpr int kLast = kChunks - 64 * (kPer - 1);  // lanes with a 4th chunk: 15
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // 16 bytes, a plain vector value
 
 // float -> bf16 bits, round to nearest even (NaN stays NaN).
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -71,11 +72,6 @@ __global__ __launch_bounds__(256) void k_split_bf16x3(const double* __restrict__
   }
 }
 
-__device__ __forceinline__ int64_t uniform64s(int64_t x) {
-  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
 
 __device__ __forceinline__ int32_t lower_bound_cs(const int64_t* prod_ptr, int32_t n, int64_t t) {
   int32_t lo = 0, hi = n;
@@ -95,8 +91,9 @@ __device__ __forceinline__ void wsync() {
 
 // Schedule as in the FP64 23x23 kernel: each XCD owns a contiguous run of C
 // blocks holding 1/8 of the products; its waves take interleaved chunks of
-// kChunk consecutive C blocks.  One LDS stage per wave: a product is written
-// to the stage after the previous one has been read.
+// kChunk consecutive C blocks.  Products are fetched two steps ahead into two
+// register slots; one LDS stage per wave, written after the previous product
+// has been read.
 __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     const uint16_t* __restrict__ As, const uint16_t* __restrict__ Bs, const double* __restrict__ Ov,
     const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
@@ -162,18 +159,22 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
       qb1 = prod_b[n1];
     }
   }
-  uint4 opa[kPer], opb[kPer];
-  auto fetch_next = [&]() {
-    if (qa0 >= 0) {
-      const uint4* Ab = reinterpret_cast<const uint4*>(As + (int64_t)qa0 * kSplitBlock) + lane;
-      const uint4* Bb = reinterpret_cast<const uint4*>(Bs + (int64_t)qb0 * kSplitBlock) + lane;
+  // two register slots, as separately named arrays (kept in registers)
+  u32x4 opa0[kPer], opb0[kPer], opa1[kPer], opb1[kPer];
+  // the next product's split blocks into a slot (a past-the-end product
+  // rereads block 0, so every fetch issues the same loads)
+  auto fetch_next = [&](u32x4(&opa)[kPer], u32x4(&opb)[kPer]) __attribute__((always_inline)) {
+    {
+      const int64_t ia = qa0 >= 0 ? qa0 : 0, ib = qa0 >= 0 ? qb0 : 0;
+      const u32x4* Ab = reinterpret_cast<const u32x4*>(As + ia * kSplitBlock) + lane;
+      const u32x4* Bb = reinterpret_cast<const u32x4*>(Bs + ib * kSplitBlock) + lane;
 #pragma unroll
       for (int u = 0; u < kPer - 1; ++u) {
         opa[u] = Ab[64 * u];
         opb[u] = Bb[64 * u];
       }
-      opa[kPer - 1] = tail ? Ab[64 * (kPer - 1)] : make_uint4(0, 0, 0, 0);
-      opb[kPer - 1] = tail ? Bb[64 * (kPer - 1)] : make_uint4(0, 0, 0, 0);
+      opa[kPer - 1] = Ab[tail ? 64 * (kPer - 1) : 0];
+      opb[kPer - 1] = Bb[tail ? 64 * (kPer - 1) : 0];
     }
     qa0 = qa1;
     qb0 = qb1;
@@ -181,15 +182,15 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     qa1 = n >= 0 ? prod_a[n] : -1;
     qb1 = n >= 0 ? prod_b[n] : -1;
   };
-  auto stage_write = [&]() {
+  auto stage_write = [&](const u32x4(&opa)[kPer], const u32x4(&opb)[kPer]) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < kPer - 1; ++u) {
-      *reinterpret_cast<uint4*>(stage + off[u]) = opa[u];
-      *reinterpret_cast<uint4*>(stage + kLdsOperand + off[u]) = opb[u];
+      *reinterpret_cast<u32x4*>(stage + off[u]) = opa[u];
+      *reinterpret_cast<u32x4*>(stage + kLdsOperand + off[u]) = opb[u];
     }
     if (tail) {
-      *reinterpret_cast<uint4*>(stage + off[kPer - 1]) = opa[kPer - 1];
-      *reinterpret_cast<uint4*>(stage + kLdsOperand + off[kPer - 1]) = opb[kPer - 1];
+      *reinterpret_cast<u32x4*>(stage + off[kPer - 1]) = opa[kPer - 1];
+      *reinterpret_cast<u32x4*>(stage + kLdsOperand + off[kPer - 1]) = opb[kPer - 1];
     }
   };
 
@@ -283,14 +284,28 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     return true;
   };
 
-  // Pipeline: product n is fetched at step n-1, written at the start of step
-  // n (after the previous product has been read) and multiplied.
-  if (qa0 >= 0) fetch_next();
+  // Pipeline: product n is fetched into slot n % 2 at step n-2, written to
+  // the stage at the start of step n (after product n-1 has been read) and
+  // multiplied; its slot then takes product n+2.
+  fetch_next(opa0, opb0);
+  fetch_next(opa1, opb1);
+  // (the two halves carry distinct markers so that the compiler does not
+  // merge them into one body indexing the slots at run time, which would put
+  // the slots in scratch memory)
   for (;;) {
     if (p == pe && !advance()) break;
+    asm volatile("; slot 0");
     wsync();
-    stage_write();
-    fetch_next();
+    stage_write(opa0, opb0);
+    fetch_next(opa0, opb0);
+    wsync();
+    multiply_stage();
+    ++p;
+    if (p == pe && !advance()) break;
+    asm volatile("; slot 1");
+    wsync();
+    stage_write(opa1, opb1);
+    fetch_next(opa1, opb1);
     wsync();
     multiply_stage();
     ++p;
