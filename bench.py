@@ -164,6 +164,11 @@ def chain_leg(nmol, steps=12, eps=1e-7, replays=3):
     X0, info = W.symmetric_scaled(nmol=nmol)
     ch = SignChain(X0, steps=steps, eps=eps)
     flops, prods, blocks = ch.count_flops()
+    # the same chain enqueued call by call (no graph), for comparison
+    t0 = time.perf_counter()
+    ch.enqueue()
+    ch.stream.synchronize()
+    dt_eager = time.perf_counter() - t0
     ch.capture()
     ch.stream.synchronize()
     t0 = time.perf_counter()
@@ -179,7 +184,7 @@ def chain_leg(nmol, steps=12, eps=1e-7, replays=3):
            "value": round(flops / dt / 1e9, 2), "unit": "GFLOP/s", "ms_per_chain": round(dt * 1e3, 3),
            "useful_gflop_per_chain": round(flops / 1e9, 3), "products_per_chain": int(prods),
            "x_blocks_per_step": blocks, "residual_fro": res,
-           "residual_rel": res / math.sqrt(n), "replays": replays}
+           "residual_rel": res / math.sqrt(n), "replays": replays, "ms_per_chain_eager": round(dt_eager * 1e3, 3)}
     ch.close()
     return out
 
@@ -192,7 +197,8 @@ def main():
     ap.add_argument("--workload", default="molecules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chain-nmol", type=int, default=256,
-                    help="molecules of the sign-chain leg (0 skips it)")
+                    help="molecules of the sign chain (--workload chain)")
+    ap.add_argument("--chain-replays", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device to device three times (calibrates the HBM traffic counters)")
     args = ap.parse_args()
@@ -215,6 +221,18 @@ def main():
     from paper_1708_03604_amd import bsmm
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.workload == "chain":
+        torch.cuda.set_device(0)
+        log(f"[bench] sign chain on {args.chain_nmol} molecules")
+        ch = chain_leg(args.chain_nmol, replays=args.chain_replays)
+        out = {"metric": "useful GFLOP/s of the Newton-Schulz sign chain (block-sparse 23x23 FP64 multiplies, "
+                         "one HIP graph)",
+               "value": ch.pop("value"), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.chain_replays, "warmup": 1,
+               "ms_per_step": ch["ms_per_chain"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic", "config": {"workload": ch.pop("workload")}, "chain": ch}
+        log(f"[bench] chain: {ch['ms_per_chain']} ms, {out['value']} GFLOP/s, residual {ch['residual_fro']:.3e}")
+        print(json.dumps(out), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"[bench] building workload {args.workload}")
@@ -283,11 +301,6 @@ def main():
         sp = out["split_bf16x3"]
         log(f"[bench] split: {sp['ms_per_step']} ms/step ({sp['speedup_vs_fp64']}x), rel Frobenius error "
             f"{sp['rel_frobenius_vs_fp64']:.2e}")
-    if args.chain_nmol > 0 and args.workload == "molecules":
-        log(f"[bench] sign chain on {args.chain_nmol} molecules")
-        out["chain"] = chain_leg(args.chain_nmol)
-        log(f"[bench] chain: {out['chain']['ms_per_chain']} ms, {out['chain']['value']} GFLOP/s, "
-            f"residual {out['chain']['residual_fro']:.3e}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, flops)
