@@ -61,7 +61,7 @@ struct DBuf {
   }
 };
 
-// Pattern + values of one matrix.  Values carry 64 doubles of slack so that
+// Pattern + values of one matrix.  Values carry kValueSlack doubles of slack so that
 // kernels may read a little past the last block (never used in results).
 struct Storage {
   DBuf<int32_t> row_ptr;

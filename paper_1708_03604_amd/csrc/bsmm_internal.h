@@ -46,8 +46,9 @@ enum : int {
   kTotCount = 8
 };
 
-// Doubles of zero slack kept after the last value of every matrix.
-constexpr int kValueSlackDoubles = 64;
+// Doubles of zero slack kept after the last value of every matrix: the
+// small-block kernel reads up to 256 values from the start of any block.
+constexpr int kValueSlackDoubles = 256;
 
 // Result blocks of the multiply whose totals these are (0 once aborted).
 __device__ __forceinline__ int32_t live_nnzc(const int64_t* totals) {

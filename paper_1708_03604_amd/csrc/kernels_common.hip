@@ -214,7 +214,8 @@ __global__ void k_finish_multiply(const int64_t* __restrict__ totals, double* __
                                   int64_t* __restrict__ dsz) {
   const int t = threadIdx.x;
   const bool ok = totals[kTotAbort] == 0;
-  if (ok && t < kValueSlackDoubles) values[totals[kTotNvals] + t] = 0.0;
+  if (ok)
+    for (int x = t; x < kValueSlackDoubles; x += 64) values[totals[kTotNvals] + x] = 0.0;
   if (t == 0) {
     dsz[0] = ok ? totals[kTotNnzc] : 0;
     dsz[1] = ok ? totals[kTotNvals] : 0;
@@ -365,7 +366,7 @@ __global__ void k_filter_finish(const int64_t* __restrict__ keep_pos, const int6
                                 int64_t bound, double* __restrict__ out_values, int64_t* __restrict__ dsz) {
   const int64_t nv = voff[bound];
   const int t = threadIdx.x;
-  if (t < kValueSlackDoubles) out_values[nv + t] = 0.0;
+  for (int x = t; x < kValueSlackDoubles; x += 64) out_values[nv + x] = 0.0;
   __syncthreads();
   if (t == 0) {
     dsz[0] = keep_pos[bound];

@@ -270,20 +270,24 @@ __device__ __forceinline__ int64_t make64(int32_t lo, int32_t hi) {
 
 // One class: C blocks list[L0, L1) padded to MP x NP, D products in flight.
 //
-// Each wave takes a contiguous run of the class list (its XCD's part of the
-// list split evenly over the XCD's waves), so both its list entries and its
-// product descriptors (stored in list order) are contiguous.  The wave walks
-// them as one stream of slots: one slot per product, and one empty slot for a
-// C block without products.  A slot carries the operand loads of its product
-// and, on the last slot of a C block, the block's finishing data.
+// Each wave takes a contiguous run of the class list (the chunks the XCD's
+// round robin gives it), so its list entries and product descriptors (stored
+// in list order) are contiguous.  The wave walks them as one stream of slots:
+// one slot per product, and one empty slot for a C block without products.
 //
-// Loads are arranged so that no wait ever stalls on a recent load: every
-// slot issues exactly RA + RB vector loads (lanes past the product's elements
-// reread its first element), so outstanding loads are counted exactly; list
-// entries and descriptors arrive in batches of 64 (one per lane, read back
-// with readlane), each batch loaded one batch ahead; and the steady state
-// issues no scalar memory loads, whose completion every LDS wait would
-// otherwise also wait for.
+// The product loop is kept short, since at a few hundred bytes per product
+// the kernel is bound by instructions issued, not by memory:
+//   - list entries and descriptors arrive in 64-wide vector batches read back
+//     with readlane, each loaded one batch ahead, and the loop issues no
+//     scalar memory loads (whose completion every LDS wait would also await);
+//   - every product issues the same RA + RB operand loads from the block start
+//     with immediate offsets (the value slack after every matrix covers the
+//     overrun), so the compiler's wait counts are exact;
+//   - a slot carries one packed word (m, n, k, valid, last); the finishing data
+//     of each C block goes into a lane-indexed queue when its entry starts and
+//     is read back when the block is finished;
+//   - B rows k .. 4*ceil(k/4)-1 are written as zeros, so the four K slices run
+//     the same number of steps with no lane masks.
 template <int MP, int NP, int D>
 __device__ __forceinline__ void small_class(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
                                             int32_t xcd, int32_t wpx, int32_t wix, int lane) {
@@ -292,13 +296,15 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   static_assert(V % 4 == 0 && D % 2 == 0, "tile shape");
   const int s = lane >> 4, rho = (lane >> 2) & 3, gam = lane & 3;
 
-  // This wave's run of the list: [E0, E1), products [Q0, Q1) in list order.
+  // This wave's run of the list: [E0, E1), products [Q0, Q0 + NQ) in list order.
   const int64_t L = L1 - L0;
   const int64_t X0 = L0 + L * xcd / kXcds, X1 = L0 + L * (xcd + 1) / kXcds;
   const int32_t E0 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix));
   const int32_t E1 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix + 1));
   if (E0 >= E1) return;
-  const int64_t Q0 = P.qstart[E0], Q1 = P.qstart[E1];
+  const int64_t Q0 = P.qstart[E0];
+  const int32_t NQ = (int32_t)(P.qstart[E1] - Q0);
+  const int4* __restrict__ dq = P.desc + Q0;
 
   // ---- entry batches: lane u holds entry eb + u (current) and eb + 64 + u (next)
   int32_t eb = E0, ei = E0;
@@ -313,26 +319,37 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   settle(cb);
   load_entries(eb + 64, na, nb);
   // ---- descriptor batches: lane u holds descriptor qb + u (current) and qb + 64 + u (next)
-  int64_t qb = Q0, qi = Q0;
+  int32_t qb = 0, qi = 0;
   int4 cd, nd;
-  auto load_desc = [&](int64_t base, int4& x) {
-    const int64_t q = base + lane < Q1 ? base + lane : (Q1 > Q0 ? Q1 - 1 : 0);
-    x = P.desc[q];
+  auto load_desc = [&](int32_t base, int4& x) {
+    const int32_t q = base + lane < NQ ? base + lane : (NQ > 0 ? NQ - 1 : 0);
+    x = dq[q];
   };
   load_desc(qb, cd);
   settle(cd);
   load_desc(qb + 64, nd);
 
-  // ---- fetch cursor: current entry (m, n, products left, finishing data)
+  // ---- finishing data of the C blocks between fetch and finish: a queue in
+  // lanes (entry w at lane w mod 64; at most D+1 blocks are open at a time)
+  int32_t fifo_mn = 0, fifo_co0 = 0, fifo_co1 = 0, fifo_oo0 = 0, fifo_oo1 = 0;
+  int32_t fw = 0, fr = 0;
+
+  // ---- fetch cursor: current entry (m, n, products left)
   bool fok = true;
-  int32_t fmn = 0, frem = 0;
-  int64_t fcoff = 0, fooff = -1;
+  int32_t fm = 0, fn = 0, frem = 0;
   auto take_entry = [&]() {
     const int u = ei - eb;
-    fmn = __builtin_amdgcn_readlane(ca.x, u);
+    const int32_t mn = __builtin_amdgcn_readlane(ca.x, u);
+    fm = mn & 255;
+    fn = mn >> 8;
     frem = __builtin_amdgcn_readlane(ca.z, u);
-    fcoff = make64(__builtin_amdgcn_readlane(cb.x, u), __builtin_amdgcn_readlane(cb.y, u));
-    fooff = make64(__builtin_amdgcn_readlane(cb.z, u), __builtin_amdgcn_readlane(cb.w, u));
+    const bool mine = lane == (fw & 63);
+    fifo_mn = mine ? mn : fifo_mn;
+    fifo_co0 = mine ? __builtin_amdgcn_readlane(cb.x, u) : fifo_co0;
+    fifo_co1 = mine ? __builtin_amdgcn_readlane(cb.y, u) : fifo_co1;
+    fifo_oo0 = mine ? __builtin_amdgcn_readlane(cb.z, u) : fifo_oo0;
+    fifo_oo1 = mine ? __builtin_amdgcn_readlane(cb.w, u) : fifo_oo1;
+    ++fw;
   };
   auto next_entry = [&]() {
     ++ei;
@@ -352,115 +369,110 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   };
   take_entry();
 
-  // ---- slots: product X lives in slot X % D from its fetch to its stage write
+  // ---- slots: product X lives in slot X % D from its fetch to its stage write.
+  // Packed word: m | n << 5 | k << 10 | valid << 15 | last << 16.
   double sa[D][RA], sb[D][RB];
-  int32_t sok[D], smk[D], skn[D], sk[D], sn[D], slast[D], smn[D];
-  int64_t scoff[D], sooff[D];
+  int32_t sw[D];
+  // masked-off lanes keep their previous values: start from zeros so that
+  // every stale value is finite (inner steps past k multiply them by zero)
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j < RA; ++j) sa[d][j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) sb[d][j] = 0.0;
+  }
   auto fetch = [&](auto slot) {
     constexpr int d = decltype(slot)::value;
     int64_t ao = 0, bo = 0;
-    int32_t mk = 0, kn = 0;
-    sok[d] = fok;
-    if (fok) {
-      const int32_t m = fmn & 255, n = fmn >> 8;
-      int32_t k = 0;
-      if (frem > 0) {
-        const int u = (int)(qi - qb);
-        const int32_t dx = __builtin_amdgcn_readlane(cd.x, u), dy = __builtin_amdgcn_readlane(cd.y, u);
-        const int32_t dz = __builtin_amdgcn_readlane(cd.z, u), dw = __builtin_amdgcn_readlane(cd.w, u);
-        ao = make64(dx, dy & 0xffffff);
-        k = (int32_t)((uint32_t)dy >> 24);
-        bo = make64(dz, dw);
-        mk = m * k;
-        kn = k * n;
-        --frem;
-        ++qi;
-        if (qi - qb == 64) {
-          qb += 64;
-          cd = nd;
-          settle(cd);
-          load_desc(qb + 64, nd);
-        }
+    int32_t k = 0;
+    if (fok && frem > 0) {
+      const int u = qi - qb;
+      const int32_t dy = __builtin_amdgcn_readlane(cd.y, u);
+      ao = make64(__builtin_amdgcn_readlane(cd.x, u), dy & 0xffffff);
+      k = (int32_t)((uint32_t)dy >> 24);
+      bo = make64(__builtin_amdgcn_readlane(cd.z, u), __builtin_amdgcn_readlane(cd.w, u));
+      --frem;
+      ++qi;
+      if (qi - qb == 64) {
+        qb += 64;
+        cd = nd;
+        settle(cd);
+        load_desc(qb + 64, nd);
       }
-      smk[d] = mk;
-      skn[d] = kn;
-      sk[d] = k;
-      sn[d] = n;
-      slast[d] = frem == 0;
-      smn[d] = fmn;
-      scoff[d] = fcoff;
-      sooff[d] = fooff;
-      if (frem == 0) next_entry();
     }
-    // RA + RB loads, always: lane l takes elements l, l+64, .. of the A
-    // block and of the B block, or the block's first element past its end
-    const double* pa = P.Av + ao;
-    const double* pb = P.Bv + bo;
+    sw[d] = fm | (fn << 5) | (k << 10) | ((int32_t)fok << 15) | ((int32_t)(frem == 0) << 16);
+    const int32_t mk = fm * k, kn = k * fn;  // before the cursor moves to the next C block
+    if (fok && frem == 0) next_entry();
+    // RA + RB loads from the block starts, always issued; lanes past the
+    // block are masked off (no traffic) and keep stale values, which never
+    // reach a stored output
+    const double* pa = P.Av + ao + lane;
+    const double* pb = P.Bv + bo + lane;
 #pragma unroll
-    for (int j = 0; j < RA; ++j) {
-      const int e = lane + 64 * j;
-      sa[d][j] = pa[e < mk ? e : 0];
-    }
+    for (int j = 0; j < RA; ++j)
+      if (lane + 64 * j < mk) sa[d][j] = pa[64 * j];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      const int e = lane + 64 * j;
-      sb[d][j] = pb[e < kn ? e : 0];
-    }
+    for (int j = 0; j < RB; ++j)
+      if (lane + 64 * j < kn) sb[d][j] = pb[64 * j];
   };
-  // what each LDS stage holds: valid slot, inner size, and the finishing data
-  // of its C block if the slot is the block's last
-  int32_t stok[2] = {0, 0}, stk[2] = {0, 0}, stn[2] = {0, 0}, stlast[2] = {0, 0}, stmn[2] = {0, 0};
-  int64_t stcoff[2] = {0, 0}, stooff[2] = {-1, -1};
+
+  // what each LDS stage holds (the packed word of its slot)
+  int32_t stw[2] = {0, 0};
   auto stage_write = [&](auto slot, auto stage) {
     constexpr int d = decltype(slot)::value;
     constexpr int st = decltype(stage)::value;
-    const int32_t mk = smk[d], kn = skn[d], k = sk[d], n = sn[d];
-    stok[st] = sok[d];
-    stk[st] = k;
-    stn[st] = n;
-    stlast[st] = slast[d];
-    stmn[st] = smn[d];
-    stcoff[st] = scoff[d];
-    stooff[st] = sooff[d];
+    const int32_t w = sw[d];
+    stw[st] = w;
+    const int32_t n = (w >> 5) & 31, k = (w >> 10) & 31;
     if (k == 0) return;
-    // A and B are copied as they are stored (row-major, dense): contiguous,
-    // bank-conflict-free writes with no index arithmetic
+    // A and B are copied as they are stored (row-major, dense); B's values
+    // past the block are written as zeros, so the rows k .. 4*ceil(k/4)-1 that
+    // the K slices reach contribute nothing
     double* As = wl + st * kStage;
     double* Bs = As + kOperand;
+    const int32_t kn = k * n;
 #pragma unroll
-    for (int j = 0; j < RA; ++j)
-      if (lane + 64 * j < mk) As[lane + 64 * j] = sa[d][j];
+    for (int j = 0; j < RA; ++j) As[lane + 64 * j] = sa[d][j];
 #pragma unroll
-    for (int j = 0; j < RB; ++j)
-      if (lane + 64 * j < kn) Bs[lane + 64 * j] = sb[d][j];
+    for (int j = 0; j < RB; ++j) Bs[lane + 64 * j] = lane + 64 * j < kn ? sb[d][j] : 0.0;
   };
 
   double acc[V];
 #pragma unroll
   for (int x = 0; x < V; ++x) acc[x] = 0.0;
-  // Lane (s, rho, gam), inner index t: A(rho*RM + i, t) = As[(rho*RM + i)*k + t]
-  // and B(t, gam*RN + j) = Bs[t*n + gam*RN + j].  Rows and columns past the
-  // block read other staged values; they only reach padded outputs.
+  // Lane (s, rho, gam), inner index t = s + 4j: A(rho*RM + i, t) = As[(rho*RM + i)*k + t]
+  // and B(t, gam*RN + jj) = Bs[t*n + gam*RN + jj].  Rows and columns past the
+  // block, and inner indices past k (where B is zero), only reach padded
+  // outputs or add zeros.
+  // The inner steps go in groups of G whose LDS reads are issued together
+  // (reads past 4*ceil(k/4) stay inside the stage and are not used).
   auto compute = [&](auto stage) {
     constexpr int st = decltype(stage)::value;
-    const int32_t k = stk[st], n = stn[st];
-    const double* As = wl + st * kStage + rho * RM * k;
-    const double* Bs = wl + st * kStage + kOperand + gam * RN;
+    constexpr int G = RM + RN <= 4 ? 4 : 2;
+    const int32_t w = stw[st];
+    const int32_t n = (w >> 5) & 31, k = (w >> 10) & 31;
+    const double* As = wl + st * kStage + rho * RM * k + s;
+    const double* Bs = wl + st * kStage + kOperand + s * n + gam * RN;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (4 * j < k) {
-        const int t = s + 4 * j;
-        if (t < k) {
-          double a[RM], b[RN];
+    for (int j0 = 0; j0 < 4; j0 += G) {
+      if (4 * j0 < k) {
+        double a[G][RM], b[G][RN];
 #pragma unroll
-          for (int i = 0; i < RM; ++i) a[i] = As[i * k + t];
+        for (int g = 0; g < G; ++g) {
 #pragma unroll
-          for (int jj = 0; jj < RN; ++jj) b[jj] = Bs[t * n + jj];
+          for (int i = 0; i < RM; ++i) a[g][i] = As[i * k + 4 * (j0 + g)];
 #pragma unroll
-          for (int i = 0; i < RM; ++i)
-#pragma unroll
-            for (int jj = 0; jj < RN; ++jj) acc[i * RN + jj] = fma(a[i], b[jj], acc[i * RN + jj]);
+          for (int jj = 0; jj < RN; ++jj) b[g][jj] = Bs[4 * (j0 + g) * n + jj];
         }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (4 * (j0 + g) < k) {
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+              for (int jj = 0; jj < RN; ++jj) acc[i * RN + jj] = fma(a[g][i], b[g][jj], acc[i * RN + jj]);
+          }
       }
     }
   };
@@ -481,7 +493,12 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
       swap16(acc[x], acc[x + V / 4]);
       acc[x] = acc[x] + acc[x + V / 4];
     }
-    const int32_t m = stmn[fs] & 255, n = stmn[fs] >> 8;
+    const int r = fr & 63;
+    ++fr;
+    const int32_t mn = __builtin_amdgcn_readlane(fifo_mn, r);
+    const int32_t m = mn & 255, n = mn >> 8;
+    const int64_t coff = make64(__builtin_amdgcn_readlane(fifo_co0, r), __builtin_amdgcn_readlane(fifo_co1, r));
+    const int64_t oo = make64(__builtin_amdgcn_readlane(fifo_oo0, r), __builtin_amdgcn_readlane(fifo_oo1, r));
     // this lane's outputs are tile slots y = (V/4)*s + x
 #pragma unroll
     for (int x = 0; x < V / 4; ++x) {
@@ -491,8 +508,7 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
     }
     wave_sync();
     const int32_t mnv = m * n;
-    double* out = P.Cv + stcoff[fs];
-    const int64_t oo = stooff[fs];
+    double* out = P.Cv + coff;
     if (oo >= 0) {
       const double* ov = P.Ov + oo;
       double ol[MP * NP / 64];
@@ -523,9 +539,11 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   stage_write(std::integral_constant<int, 0>(), std::integral_constant<int, 0>());
   fetch(std::integral_constant<int, 0>());
 
-  // Step i (slot n = i mod D, in stage n & 1): write slot n+1 into the other
-  // stage, refill its register slot with slot n+1+D, multiply slot n, and if
-  // slot n ends its C block, finish the block.
+  // Step i (slot n = i mod D, in stage n & 1): multiply slot n, write slot
+  // n+1 into the other stage and refill its register slot with slot n+1+D,
+  // then wait for the stage writes (the next step reads them); if slot n ends
+  // its C block, finish the block in its stage.
+  wave_sync();
   bool more = true;
   while (more) {
     static_for<0, D>([&](auto idx) {
@@ -533,23 +551,21 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
       constexpr int nx = (i + 1) % D;
       constexpr int st = i & 1;
       if (!more) return;
-      if (!stok[st]) {
+      const int32_t w = stw[st];
+      if (!((w >> 15) & 1)) {
         more = false;
         return;
       }
+      compute(std::integral_constant<int, st>());
       stage_write(std::integral_constant<int, nx>(), std::integral_constant<int, st ^ 1>());
       fetch(std::integral_constant<int, nx>());
       wave_sync();
-      compute(std::integral_constant<int, st>());
-      if (stlast[st]) {
-        wave_sync();
-        finish(std::integral_constant<int, st>());
-      }
+      if ((w >> 16) & 1) finish(std::integral_constant<int, st>());
     });
   }
 }
 
-__global__ __launch_bounds__(256) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
+__global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
                                                        const int32_t* __restrict__ cls_start,
                                                        const int64_t* __restrict__ qstart,
