@@ -62,6 +62,17 @@ typedef enum {
 
 enum { BSMM_PTR_HOST = 0, BSMM_PTR_DEVICE = 1 };
 
+/* Kernel path that computed the block products of a multiply. */
+enum {
+  BSMM_PATH_GENERIC = 0, /* any block sizes, FP64 */
+  BSMM_PATH_TILE23 = 1,  /* uniform 23x23 blocks, FP64 */
+  BSMM_PATH_SMALL = 2,   /* every block edge <= 16, FP64, one launch over all shape classes */
+  BSMM_PATH_SPLIT23 = 3  /* uniform 23x23 blocks, BSMM_SPLIT_BF16X3 */
+};
+
+/* Number of compiled pipeline variants of the small-block path. */
+#define BSMM_SMALL_VARIANTS 6
+
 /* Counters of the last multiply that wrote a handle. */
 typedef struct {
   int64_t candidates;  /* block products with both blocks present (before the filter) */
@@ -69,6 +80,8 @@ typedef struct {
   int64_t nnzb;        /* blocks in the result */
   int64_t nvals;       /* values in the result */
   double useful_flops; /* sum over kept products of 2*m*n*k */
+  int32_t path;        /* BSMM_PATH_* */
+  int32_t variant;     /* small-block pipeline variant used (-1 on other paths) */
 } bsmm_mult_stats;
 
 /*
@@ -159,6 +172,54 @@ bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t*
 /* Counters of the last multiply that wrote C (zeros if none).  Waits for the
  * device like bsmm_info when C is device-sized. */
 bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
+
+/*
+ * Autotuner of the small-block path (Section 2: the batched multiply is tuned
+ * for each set of block dimensions).  The path pads each block to a shape
+ * class, 8 or 16 rows by 8 or 16 columns, and keeps a number of block
+ * products in flight per wave; a pipeline variant fixes that number per
+ * class (bsmm_small_variant).  The tuning table maps a tuning key (the block
+ * edges present in A's rows, A's columns and B's columns) to a variant;
+ * multiplies whose key has no entry use variant 1.
+ *
+ * bsmm_tune_small computes C_out = alpha*A*B + beta*C_in exactly as
+ * bsmm_multiply with BSMM_FP64 does, then, if the small-block path served it,
+ * times the products of each class alone with every variant (`reps` launches
+ * each, HIP events on `stream`), enters the variant with the least total time
+ * into the table and leaves C_out as that variant computes it (all variants
+ * give identical values).  Arguments as bsmm_multiply, plus:
+ *   reps        : launches per variant and class, 1 ..  1000
+ *   variant_out : chosen variant, or -1 when another path serves these sizes
+ *                 (then nothing is timed and the table is unchanged)
+ *   ms_out      : NULL, or host array [BSMM_SMALL_VARIANTS * 4] receiving
+ *                 the milliseconds of variant v, class c at [4*v + c],
+ *                 summed over the reps
+ * C_in must not be C_out (BSMM_E_ARG), and C_out must not be reserved.
+ * Synchronises `stream`.
+ */
+bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C_out,
+                            double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream);
+
+/* Products kept in flight per wave by variant v in the classes 8x8, 8x16,
+ * 16x8 and 16x16 (rows x columns) into depths[4]; BSMM_E_ARG if v is out of
+ * range. */
+bsmm_status bsmm_small_variant(int32_t v, int32_t* depths);
+
+/* Tuning key of the product A*B: bits e-1, 16+e-1 and 32+e-1 are set for each
+ * block edge e in A's row sizes, A's column sizes and B's column sizes.
+ * BSMM_E_UNSUPPORTED if an edge exceeds 16 (the small-block path does not
+ * serve such sizes). */
+bsmm_status bsmm_tune_key(bsmm_mat A, bsmm_mat B, uint64_t* key);
+
+/* Table entry of `key`: bsmm_tune_set enters `variant` (0 .. BSMM_SMALL_VARIANTS-1)
+ * or removes the entry (variant < 0); bsmm_tune_get returns it, -1 if none.
+ * The table is process-wide and guarded by a lock. */
+bsmm_status bsmm_tune_set(uint64_t key, int32_t variant);
+bsmm_status bsmm_tune_get(uint64_t key, int32_t* variant);
+
+/* Copy up to `cap` table entries (ascending key) into keys[] / variants[]
+ * (host arrays); *n receives the number of entries in the table. */
+bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, int32_t* n);
 
 /*
  * Graph-capturable mode.  Reserve device capacity in m for the results of the

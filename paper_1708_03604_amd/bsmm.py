@@ -23,6 +23,11 @@ BSMM_SPLIT_F32X2 = 1
 BSMM_SPLIT_BF16X3 = 2
 BSMM_PTR_HOST = 0
 BSMM_PTR_DEVICE = 1
+BSMM_PATH_GENERIC = 0
+BSMM_PATH_TILE23 = 1
+BSMM_PATH_SMALL = 2
+BSMM_PATH_SPLIT23 = 3
+BSMM_SMALL_VARIANTS = 6
 
 
 class BsmmError(RuntimeError):
@@ -34,11 +39,13 @@ class BsmmError(RuntimeError):
 
 class MultStats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("products", ctypes.c_int64), ("nnzb", ctypes.c_int64),
-                ("nvals", ctypes.c_int64), ("useful_flops", ctypes.c_double)]
+                ("nvals", ctypes.c_int64), ("useful_flops", ctypes.c_double), ("path", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
 
 
 # every function declared in include/bsmm.h, with its ctypes signature
 _vp, _i32, _i64, _dbl, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+_u64 = ctypes.c_uint64
 SIGNATURES = {
     "bsmm_create": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _int, _vp], _int),
     "bsmm_destroy": ([_vp], _int),
@@ -58,6 +65,12 @@ SIGNATURES = {
     "bsmm_capture_end": ([_vp, _vp], _int),
     "bsmm_graph_launch": ([_vp, _vp], _int),
     "bsmm_graph_destroy": ([_vp], _int),
+    "bsmm_tune_small": ([_dbl, _vp, _vp, _dbl, _vp, _vp, _dbl, _i32, _vp, _vp, _vp], _int),
+    "bsmm_small_variant": ([_i32, _vp], _int),
+    "bsmm_tune_key": ([_vp, _vp, _vp], _int),
+    "bsmm_tune_set": ([_u64, _i32], _int),
+    "bsmm_tune_get": ([_u64, _vp], _int),
+    "bsmm_tune_entries": ([_vp, _vp, _i32, _vp], _int),
 }
 
 _lib = None
@@ -75,6 +88,9 @@ def lib():
             f.argtypes = args
             f.restype = res
         _lib = L
+        from . import tune
+        if os.path.exists(tune.TABLE):
+            tune.load(tune.TABLE)
     return _lib
 
 
@@ -224,6 +240,46 @@ def bsmm_graph_launch(g, stream=None):
 
 def bsmm_graph_destroy(g):
     _check("bsmm_graph_destroy", lib().bsmm_graph_destroy(g))
+
+
+def bsmm_tune_small(alpha, A, B, beta, C_in, C_out, filter_eps, reps=5, stream=None):
+    """Returns (chosen variant or -1, per variant and class milliseconds [6, 4])."""
+    v = ctypes.c_int32()
+    ms = np.zeros((BSMM_SMALL_VARIANTS, 4), dtype=np.float64)
+    _check("bsmm_tune_small", lib().bsmm_tune_small(float(alpha), A, B, float(beta), C_in, C_out, float(filter_eps),
+                                                    int(reps), ctypes.byref(v), ms.ctypes.data, _stream(stream)))
+    return v.value, ms
+
+
+def bsmm_small_variant(v):
+    d = np.zeros(4, dtype=np.int32)
+    _check("bsmm_small_variant", lib().bsmm_small_variant(int(v), d.ctypes.data))
+    return d.tolist()
+
+
+def bsmm_tune_key(A, B):
+    k = ctypes.c_uint64()
+    _check("bsmm_tune_key", lib().bsmm_tune_key(A, B, ctypes.byref(k)))
+    return k.value
+
+
+def bsmm_tune_set(key, variant):
+    _check("bsmm_tune_set", lib().bsmm_tune_set(int(key), int(variant)))
+
+
+def bsmm_tune_get(key):
+    v = ctypes.c_int32()
+    _check("bsmm_tune_get", lib().bsmm_tune_get(int(key), ctypes.byref(v)))
+    return v.value
+
+
+def bsmm_tune_entries():
+    n = ctypes.c_int32()
+    _check("bsmm_tune_entries", lib().bsmm_tune_entries(None, None, 0, ctypes.byref(n)))
+    keys = np.zeros(max(n.value, 1), dtype=np.uint64)
+    vs = np.zeros(max(n.value, 1), dtype=np.int32)
+    _check("bsmm_tune_entries", lib().bsmm_tune_entries(keys.ctypes.data, vs.ctypes.data, n.value, ctypes.byref(n)))
+    return dict(zip(keys[:n.value].tolist(), vs[:n.value].tolist()))
 
 
 # ------------------------------------------------------------ convenience

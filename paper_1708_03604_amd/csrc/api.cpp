@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -89,6 +91,7 @@ struct bsmm_matrix {
   int64_t nvals = 0;
   int uniform = 0;  // common block edge if every row and column size is equal, else 0
   int max_edge = 0; // largest row or column block size
+  uint32_t row_edges = 0, col_edges = 0;  // bit e-1 set for each block edge e (edges above 32 set bit 31)
   Storage cur, spare;
   // product stack of the last multiply that wrote this matrix
   DBuf<int64_t> prod_ptr;
@@ -114,6 +117,7 @@ struct bsmm_matrix {
   DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
   DBuf<int64_t> class_cnt, class_pre, class_np, class_q;
   DBuf<int32_t> class_start;
+  NumArgs small_args{};  // arguments of the last small-block launch (re-launched by the tuner)
   int64_t* h_totals = nullptr;  // pinned, kPinned entries
   // phase timing: 7 events per recorded multiply
   bool timing = false;
@@ -211,6 +215,7 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
     m->nprod = 0;
     m->has_stack = false;
     m->stats = bsmm_mult_stats{};
+    m->stats.variant = -1;
     const int64_t zero[3] = {0, 0, 0};
     HIP_TRY(hipMemsetAsync(m->cur.row_ptr.p, 0, sizeof(int32_t) * (m->nbrows + 1), s));
     HIP_TRY(hipMemsetAsync(m->cur.blk_off.p, 0, sizeof(int64_t), s));
@@ -234,6 +239,29 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
   m->stats.useful_flops = 2.0 * (double)t[kTotFlopHalf];
   return BSMM_OK;
 }
+
+// Tuning table of the small-block path: tuning key -> pipeline variant.
+std::mutex g_tune_mu;
+std::map<uint64_t, int32_t> g_tune;
+
+uint64_t tune_key(const bsmm_matrix* A, const bsmm_matrix* B) {
+  return (uint64_t)(A->row_edges & 0xffffu) | (uint64_t)(A->col_edges & 0xffffu) << 16 |
+         (uint64_t)(B->col_edges & 0xffffu) << 32;
+}
+
+int32_t tuned_variant(uint64_t key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? kSmallDefault : it->second;
+}
+
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~EventPair() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
 
 }  // namespace
 
@@ -286,6 +314,9 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
   m->uniform = u;
   for (int32_t i = 0; i < nbrows; ++i) m->max_edge = std::max(m->max_edge, row_sizes[i]);
   for (int32_t j = 0; j < nbcols; ++j) m->max_edge = std::max(m->max_edge, col_sizes[j]);
+  for (int32_t i = 0; i < nbrows; ++i) m->row_edges |= 1u << (std::min(row_sizes[i], 32) - 1);
+  for (int32_t j = 0; j < nbcols; ++j) m->col_edges |= 1u << (std::min(col_sizes[j], 32) - 1);
+  m->stats.variant = -1;
   m->nnzb = nnzb;
   m->nvals = nvals;
   auto cleanup = [&](bsmm_status code, const std::string& msg) {
@@ -670,6 +701,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_a = C->prod_a.p;
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
+  int32_t variant = -1;
   if (split) {
     HIP_TRY(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
     HIP_TRY(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
@@ -677,7 +709,10 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   } else if (small) {
     HIP_TRY(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
-    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, s));
+    variant = tuned_variant(tune_key(A, B));
+    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, variant,
+                                 kSmallAllClasses, s));
+    C->small_args = na;
   } else {
     HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
   }
@@ -687,6 +722,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
 
   if (in_place) std::swap(C->cur, C->spare);
   C->has_stack = true;
+  C->stats.path = split ? BSMM_PATH_SPLIT23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
+  C->stats.variant = variant;
   if (reserved) return BSMM_OK;
   C->nnzb = (int32_t)nnzc;
   C->nvals = nvals;
@@ -853,6 +890,111 @@ bsmm_status bsmm_graph_destroy(bsmm_graph g) {
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
   delete g;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C,
+                            double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream) {
+  g_err.clear();
+  if (!variant_out) return fail(BSMM_E_ARG, "NULL variant_out");
+  if (reps < 1 || reps > 1000) return fail(BSMM_E_ARG, "reps must be in 1 .. 1000");
+  if (C && C == C_in && beta != 0.0) return fail(BSMM_E_ARG, "tuning needs C_in distinct from C_out");
+  if (C && C->cap_nnzb > 0) return fail(BSMM_E_ARG, "tuning does not take a reserved output");
+  bsmm_status st = bsmm_multiply(alpha, A, B, beta, C_in, C, filter_eps, BSMM_FP64, stream);
+  if (st != BSMM_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  *variant_out = -1;
+  if (ms_out) std::fill(ms_out, ms_out + 4 * kSmallVariants, 0.0);
+  if (C->stats.path != BSMM_PATH_SMALL) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return BSMM_OK;
+  }
+  // Each launch recomputes C_out's values from A, B and C_in (never from
+  // C_out itself), so repeated launches leave the same result.
+  const NumArgs& na = C->small_args;
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.e[0]));
+  HIP_TRY(hipEventCreate(&ev.e[1]));
+  double total[kSmallVariants];
+  for (int32_t v = 0; v < kSmallVariants; ++v) {
+    total[v] = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      HIP_TRY(hipEventRecord(ev.e[0], s));
+      for (int32_t r = 0; r < reps; ++r)
+        HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, v, 1 << c,
+                                     s));
+      HIP_TRY(hipEventRecord(ev.e[1], s));
+      HIP_TRY(hipEventSynchronize(ev.e[1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+      total[v] += ms;
+      if (ms_out) ms_out[4 * v + c] = ms;
+    }
+  }
+  int32_t best = 0;
+  for (int32_t v = 1; v < kSmallVariants; ++v)
+    if (total[v] < total[best]) best = v;
+  HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, best,
+                               kSmallAllClasses, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(A, B)] = best;
+  }
+  C->stats.variant = best;
+  *variant_out = best;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_small_variant(int32_t v, int32_t* depths) {
+  g_err.clear();
+  if (!depths) return fail(BSMM_E_ARG, "NULL depths");
+  if (v < 0 || v >= kSmallVariants) return fail(BSMM_E_ARG, "variant out of range");
+  small_variant_depths(v, depths);
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_key(bsmm_mat A, bsmm_mat B, uint64_t* key) {
+  g_err.clear();
+  if (!A || !B || !key) return fail(BSMM_E_ARG, "NULL argument");
+  if (std::max(A->max_edge, B->max_edge) > kSmallEdge)
+    return fail(BSMM_E_UNSUPPORTED, "a block edge exceeds " + std::to_string(kSmallEdge));
+  *key = tune_key(A, B);
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_set(uint64_t key, int32_t variant) {
+  g_err.clear();
+  if (variant >= kSmallVariants) return fail(BSMM_E_ARG, "variant out of range");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (variant < 0)
+    g_tune.erase(key);
+  else
+    g_tune[key] = variant;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_get(uint64_t key, int32_t* variant) {
+  g_err.clear();
+  if (!variant) return fail(BSMM_E_ARG, "NULL variant");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  *variant = it == g_tune.end() ? -1 : it->second;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, int32_t* n) {
+  g_err.clear();
+  if (!n || cap < 0 || (cap > 0 && (!keys || !variants))) return fail(BSMM_E_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int32_t i = 0;
+  for (const auto& kv : g_tune) {
+    if (i >= cap) break;
+    keys[i] = kv.first;
+    variants[i] = kv.second;
+    ++i;
+  }
+  *n = (int32_t)g_tune.size();
   return BSMM_OK;
 }
 

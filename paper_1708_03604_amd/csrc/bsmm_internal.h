@@ -148,8 +148,16 @@ int64_t class_list_tmp_elems(int64_t nnzc_bound);  // entries of cnt and cnt_pre
 int64_t class_entries(int64_t nnzc_bound);
 hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, int64_t* tmp, int4* list,
                               int32_t* cls_start, int64_t* cnp, int64_t* qstart, int4* desc, hipStream_t s);
+// Pipeline variants of the small-block kernel: variant v keeps
+// small_variant_depths(v)[c] products in flight in class c.  `mask` selects
+// the classes to run (bit c = class c): all of them in a multiply, one at a
+// time when tuning.  kSmallDefault is the untuned choice.
+constexpr int32_t kSmallVariants = 6;
+constexpr int32_t kSmallDefault = 1;  // 4 in flight for 8x8, 2 for the others
+constexpr int32_t kSmallAllClasses = 15;
+void small_variant_depths(int32_t v, int32_t* depths);
 hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int64_t* qstart,
-                                const int4* desc, hipStream_t s);
+                                const int4* desc, int32_t variant, int32_t mask, hipStream_t s);
 
 // Split precision (23x23 blocks): FP64 values -> three BF16 terms per value,
 // split_elems(nblocks) uint16 per matrix; transpose = 1 stores each block

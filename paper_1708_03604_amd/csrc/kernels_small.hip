@@ -565,12 +565,17 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   }
 }
 
+// One persistent launch over every class: each wave runs its share of the
+// classes selected by `mask` (bit c = class c) in turn.  D0, D1, D2 are the
+// products in flight of the 8x8, 8x16 and 16x8 classes (16x16 always holds 2:
+// four 16x16 slots do not fit beside its accumulators).
+template <int D0, int D1, int D2>
 __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
                                                        const int32_t* __restrict__ cls_start,
                                                        const int64_t* __restrict__ qstart,
                                                        const int4* __restrict__ desc, double* __restrict__ Cv,
-                                                       double alpha, double beta) {
+                                                       double alpha, double beta, int32_t mask) {
   __shared__ __align__(16) double lds[4][2 * kStage];
   const SmallOps P{Av, Bv, Ov, list, qstart, desc, Cv, alpha, beta};
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -581,11 +586,12 @@ __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restri
   int32_t b[5];
 #pragma unroll
   for (int x = 0; x < 5; ++x) b[x] = cls_start[x];
-  small_class<8, 8, 4>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
-  small_class<8, 16, 2>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
-  small_class<16, 8, 2>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
-  small_class<16, 16, 2>(P, wl, b[3], b[4], xcd, wpx, wix, lane);
+  if (mask & 1) small_class<8, 8, D0>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+  if (mask & 2) small_class<8, 16, D1>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
+  if (mask & 4) small_class<16, 8, D2>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
+  if (mask & 8) small_class<16, 16, 2>(P, wl, b[3], b[4], xcd, wpx, wix, lane);
 }
+
 
 }  // namespace
 
@@ -632,12 +638,27 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
   return hipGetLastError();
 }
 
+// Compiled pipeline variants, indexed by the tuner's variant number.
+using SmallKernel = void (*)(const double*, const double*, const double*, const int4*, const int32_t*,
+                            const int64_t*, const int4*, double*, double, double, int32_t);
+constexpr SmallKernel kSmallKernels[] = {k_numeric_small<2, 2, 2>, k_numeric_small<4, 2, 2>, k_numeric_small<6, 2, 2>,
+                                         k_numeric_small<4, 4, 2>, k_numeric_small<4, 2, 4>, k_numeric_small<4, 4, 4>};
+
+constexpr int kSmallDepths[][4] = {{2, 2, 2, 2}, {4, 2, 2, 2}, {6, 2, 2, 2}, {4, 4, 2, 2}, {4, 2, 4, 2}, {4, 4, 4, 2}};
+static_assert(sizeof(kSmallKernels) / sizeof(kSmallKernels[0]) == kSmallVariants, "variant table");
+static_assert(sizeof(kSmallDepths) / sizeof(kSmallDepths[0]) == kSmallVariants, "variant table");
+
+void small_variant_depths(int32_t v, int32_t* depths) {
+  for (int c = 0; c < 4; ++c) depths[c] = (v >= 0 && v < kSmallVariants) ? kSmallDepths[v][c] : 0;
+}
+
 hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int64_t* qstart,
-                                const int4* desc, hipStream_t s) {
+                                const int4* desc, int32_t variant, int32_t mask, hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_numeric_small, dim3(small_grid()), dim3(256), 0, s, a.A.values, a.B.values,
+  if (variant < 0 || variant >= kSmallVariants) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kSmallKernels[variant], dim3(small_grid()), dim3(256), 0, s, a.A.values, a.B.values,
                      a.use_old ? a.Cin.values : a.c_values, list, cls_start, qstart, desc, a.c_values, a.alpha,
-                     a.beta);
+                     a.beta, mask & kSmallAllClasses);
   return hipGetLastError();
 }
 

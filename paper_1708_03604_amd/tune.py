@@ -1,0 +1,99 @@
+"""Autotuner of the small-block path and its table.
+
+The small-block kernel pads every block to one of four shape classes
+(8 or 16 rows by 8 or 16 columns) and runs all classes in one persistent
+launch; a pipeline variant fixes how many block products each wave keeps in
+flight per class.  Section 2 of the paper tunes the batched multiply for each
+set of block dimensions; here the tuner times every variant on each class of
+a real product (bsmm_tune_small) and keeps the fastest in a table keyed by the
+block edges of A's rows, A's columns and B's columns.
+
+The table is saved as JSON, one entry per edge set:
+
+    {"arch": "gfx950", "entries": [{"rows": [5, 13], "inner": [5, 13],
+      "cols": [5, 13], "variant": 1, "depths": [4, 2, 2, 2], "ms": [...]}]}
+
+`load()` enters a saved table into the library; the package loads
+tune_gfx950.json next to this file, if present, when the library is first
+used.
+
+    python -m paper_1708_03604_amd.tune [--nmol 3000] [--reps 5]
+
+tunes the atom-blocked water product (O: 13, H: 5) and writes the table.
+"""
+import argparse
+import json
+import os
+
+from . import bsmm
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json")
+
+
+def key_edges(key):
+    """Tuning key -> (row edges, inner edges, column edges)."""
+    return tuple([e + 1 for e in range(16) if (key >> (16 * part + e)) & 1] for part in range(3))
+
+
+def edges_key(rows, inner, cols):
+    key = 0
+    for part, edges in enumerate((rows, inner, cols)):
+        for e in edges:
+            if not 1 <= int(e) <= 16:
+                raise ValueError(f"block edge {e} outside 1..16")
+            key |= 1 << (16 * part + int(e) - 1)
+    return key
+
+
+def tune(alpha, A, B, beta, C_in, C_out, eps, reps=5, stream=None):
+    """Tune on one product (Matrix wrappers); C_out receives the product.
+    Returns the table entry (None if the small-block path does not serve it)."""
+    v, ms = bsmm.bsmm_tune_small(alpha, A.handle, B.handle, beta, C_in.handle if C_in is not None else None,
+                                 C_out.handle, eps, reps, stream)
+    if v < 0:
+        return None
+    rows, inner, cols = key_edges(bsmm.bsmm_tune_key(A.handle, B.handle))
+    return {"rows": rows, "inner": inner, "cols": cols, "variant": int(v),
+            "depths": bsmm.bsmm_small_variant(v), "ms": [[round(x / reps, 5) for x in r] for r in ms.tolist()]}
+
+
+def load(path=TABLE):
+    """Enter a saved table into the library; returns its entries."""
+    with open(path) as f:
+        table = json.load(f)
+    entries = table.get("entries", [])
+    for e in entries:
+        bsmm.bsmm_tune_set(edges_key(e["rows"], e["inner"], e["cols"]), int(e["variant"]))
+    return entries
+
+
+def save(entries, path=TABLE, note=""):
+    with open(path, "w") as f:
+        json.dump({"arch": "gfx950", "note": note, "entries": entries}, f, indent=1)
+        f.write("\n")
+
+
+def main():
+    import torch
+    from . import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nmol", type=int, default=3000)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args()
+    w = W.water_atoms(nmol=args.nmol)
+    st = torch.cuda.Stream()
+    dA = bsmm.Matrix.from_csr(w.A, st)
+    dB = bsmm.Matrix.from_csr(w.B, st)
+    dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, st)
+    entry = tune(w.alpha, dA, dB, w.beta, None, dC, w.eps, args.reps, st)
+    if entry is None:
+        raise SystemExit("the small-block path does not serve this product")
+    print(json.dumps(entry), flush=True)
+    save([entry], args.out, note=f"tuned on {w.name}, {args.reps} launches per variant and class; ms per launch")
+    for m in (dA, dB, dC):
+        m.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -53,3 +53,46 @@ def test_host_side_validation_without_device():
         bsmm.bsmm_create(2, 1, np.array([2, 0], dtype=np.int32), cs, 0, np.zeros(3, dtype=np.int32), None, None,
                          bsmm.BSMM_PTR_HOST)
     assert e.value.status == "BSMM_E_ARG"
+
+
+def test_tuning_table_without_device():
+    from paper_1708_03604_amd import tune
+    bsmm.lib()
+    depths = [bsmm.bsmm_small_variant(v) for v in range(bsmm.BSMM_SMALL_VARIANTS)]
+    assert len(set(map(tuple, depths))) == bsmm.BSMM_SMALL_VARIANTS
+    assert depths[1] == [4, 2, 2, 2]  # the untuned choice
+    for d in depths:
+        assert all(x in (2, 4, 6) for x in d) and d[3] == 2
+    with pytest.raises(bsmm.BsmmError):
+        bsmm.bsmm_small_variant(bsmm.BSMM_SMALL_VARIANTS)
+    key = tune.edges_key([5, 13], [13], [1, 16])
+    assert key == (1 << 4) | (1 << 12) | (1 << (16 + 12)) | (1 << 32) | (1 << 47)
+    assert tune.key_edges(key) == ([5, 13], [13], [1, 16])
+    with pytest.raises(ValueError):
+        tune.edges_key([17], [1], [1])
+    saved = bsmm.bsmm_tune_entries()
+    try:
+        bsmm.bsmm_tune_set(key, 3)
+        assert bsmm.bsmm_tune_get(key) == 3
+        assert bsmm.bsmm_tune_entries()[key] == 3
+        bsmm.bsmm_tune_set(key, -1)
+        assert bsmm.bsmm_tune_get(key) == -1 and key not in bsmm.bsmm_tune_entries()
+        with pytest.raises(bsmm.BsmmError) as e:
+            bsmm.bsmm_tune_set(key, bsmm.BSMM_SMALL_VARIANTS)
+        assert e.value.status == "BSMM_E_ARG"
+    finally:
+        assert bsmm.bsmm_tune_entries() == saved
+
+
+def test_saved_tuning_table():
+    from paper_1708_03604_amd import tune
+    if not os.path.exists(tune.TABLE):
+        pytest.skip("no saved table")
+    bsmm.lib()  # loads the saved table
+    import json
+    table = json.load(open(tune.TABLE))
+    assert table["arch"] == "gfx950"
+    for e in table["entries"]:
+        assert 0 <= e["variant"] < bsmm.BSMM_SMALL_VARIANTS
+        assert e["depths"] == bsmm.bsmm_small_variant(e["variant"])
+        assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variant"]

@@ -1,0 +1,131 @@
+"""Autotuner of the small-block path, through the C-ABI.
+
+Every pipeline variant computes each C element with the same operations in
+the same order, so all variants must give identical bits, and those bits must
+match the oracle to the FP64 tolerance.  The tuner must leave C as a plain
+multiply does and enter its choice into the table that later multiplies use.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_03604_amd import bsmm, tune
+from paper_1708_03604_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-12
+
+# every class of the small-block path: (8|16) x (8|16) with k in 1..16
+SIZES = ([5, 13, 13, 5, 16, 1, 9] * 4, [13, 5, 5, 13, 8, 16] * 4, [5, 13, 5, 2, 15] * 5)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture()
+def table():
+    """Restore the process-wide tuning table after the test."""
+    saved = bsmm.bsmm_tune_entries()
+    yield
+    for k in bsmm.bsmm_tune_entries():
+        bsmm.bsmm_tune_set(k, -1)
+    for k, v in saved.items():
+        bsmm.bsmm_tune_set(k, v)
+
+
+def operands(seed, beta):
+    rs, ks, cs = SIZES
+    A = W.random_matrix(seed, rs, ks, 0.35)
+    B = W.random_matrix(seed + 1, ks, cs, 0.35)
+    Co = W.random_matrix(seed + 2, rs, cs, 0.3) if beta else None
+    return A, B, Co
+
+
+def rel_err(got, ref):
+    n = np.linalg.norm(ref)
+    return np.linalg.norm(got - ref) / n if n > 0 else np.linalg.norm(got)
+
+
+def test_every_variant_gives_the_same_bits(table):
+    A, B, Co = operands(401, 1.0)
+    ref = oracle.multiply(0.75, A, B, -0.5, Co, 0.0)
+    dA, dB, dCin = bsmm.Matrix.from_csr(A), bsmm.Matrix.from_csr(B), bsmm.Matrix.from_csr(Co)
+    key = bsmm.bsmm_tune_key(dA.handle, dB.handle)
+    first = None
+    for v in range(bsmm.BSMM_SMALL_VARIANTS):
+        bsmm.bsmm_tune_set(key, v)
+        dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
+        bsmm.multiply(0.75, dA, dB, -0.5, dCin, dC, 0.0)
+        s = bsmm.bsmm_stats(dC.handle)
+        assert s["path"] == bsmm.BSMM_PATH_SMALL and s["variant"] == v
+        rp, ci, vals = dC.to_host()
+        assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx)
+        assert rel_err(vals, ref.values) <= REL_TOL
+        if first is None:
+            first = vals
+        else:
+            assert np.array_equal(vals, first), f"variant {v} differs from variant 0"
+        dC.close()
+    for m in (dA, dB, dCin):
+        m.close()
+
+
+def test_tuner_result_and_table(table):
+    A, B, Co = operands(411, 1.0)
+    ref = oracle.multiply(1.0, A, B, 1.0, Co, 0.0)
+    dA, dB, dCin = bsmm.Matrix.from_csr(A), bsmm.Matrix.from_csr(B), bsmm.Matrix.from_csr(Co)
+    dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
+    key = bsmm.bsmm_tune_key(dA.handle, dB.handle)
+    bsmm.bsmm_tune_set(key, -1)
+    entry = tune.tune(1.0, dA, dB, 1.0, dCin, dC, 0.0, reps=2)
+    v = entry["variant"]
+    assert 0 <= v < bsmm.BSMM_SMALL_VARIANTS
+    assert entry["depths"] == bsmm.bsmm_small_variant(v)
+    assert tune.edges_key(entry["rows"], entry["inner"], entry["cols"]) == key
+    ms = np.array(entry["ms"])
+    assert ms.shape == (bsmm.BSMM_SMALL_VARIANTS, 4) and np.all(ms > 0)
+    assert bsmm.bsmm_tune_get(key) == v
+    assert bsmm.bsmm_stats(dC.handle)["variant"] == v
+    rp, ci, vals = dC.to_host()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx)
+    assert rel_err(vals, ref.values) <= REL_TOL
+    # a later multiply with the same edge sets uses the tuned variant, same bits
+    dC2 = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
+    bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC2, 0.0)
+    assert bsmm.bsmm_stats(dC2.handle)["variant"] == v
+    assert np.array_equal(dC2.to_host()[2], vals)
+    for m in (dA, dB, dCin, dC, dC2):
+        m.close()
+
+
+def test_tuner_other_paths_and_errors(table):
+    sizes = [23] * 6
+    A = bsmm.Matrix.from_csr(W.random_matrix(421, sizes, sizes, 0.5))
+    C = bsmm.Matrix.empty(sizes, sizes)
+    before = bsmm.bsmm_tune_entries()
+    v, ms = bsmm.bsmm_tune_small(1.0, A.handle, A.handle, 0.0, None, C.handle, 0.0, 2)
+    assert v == -1 and not ms.any() and bsmm.bsmm_tune_entries() == before
+    assert bsmm.bsmm_stats(C.handle)["path"] == bsmm.BSMM_PATH_TILE23
+    with pytest.raises(bsmm.BsmmError) as e:
+        bsmm.bsmm_tune_key(A.handle, A.handle)
+    assert e.value.status == "BSMM_E_UNSUPPORTED"
+    S = W.random_matrix(422, [5, 13] * 3, [5, 13] * 3, 0.5)
+    dS = bsmm.Matrix.from_csr(S)
+    dT = bsmm.Matrix.from_csr(S)
+    for reps in (0, 1001):
+        with pytest.raises(bsmm.BsmmError) as e:
+            bsmm.bsmm_tune_small(1.0, dS.handle, dS.handle, 0.0, None, dT.handle, 0.0, reps)
+        assert e.value.status == "BSMM_E_ARG"
+    with pytest.raises(bsmm.BsmmError) as e:
+        bsmm.bsmm_tune_small(1.0, dS.handle, dS.handle, 1.0, dT.handle, dT.handle, 0.0, 1)
+    assert e.value.status == "BSMM_E_ARG"
+    for m in (A, C, dS, dT):
+        m.close()
