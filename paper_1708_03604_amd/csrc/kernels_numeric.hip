@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
   // consecutive C blocks, interleaved, so at any time the XCD works on a few
   // consecutive C block rows and their A blocks stay in its L2.
   constexpr int kXcds = 8;
-  constexpr int kChunk = 8;
+  constexpr int kChunk = 2;
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;  // waves per XCD
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);

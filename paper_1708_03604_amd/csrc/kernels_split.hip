@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
 
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
-  constexpr int kXcds = 8, kChunk = 8;
+  constexpr int kXcds = 8, kChunk = 2;
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
