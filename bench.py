@@ -2,7 +2,8 @@
 on one MI355X, FP64, on the molecule-blocked workload (2048 water molecules as
 23x23 blocks, 6 A cutoff, filter_eps = 1e-6, beta = 1 with C on A's pattern).
 
-    python bench.py [--steps K] [--warmup W] [--workload molecules|grid|water]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload molecules|grid|water|semi_empirical|mixed_dense|sweep|chain]
 
 A step is one bsmm_multiply (norms, symbolic count, sizing, symbolic fill,
 numeric with the alpha/beta epilogue) with inputs resident in HBM.  Prints one
@@ -66,9 +67,63 @@ def make_workload(name):
         w = W.water_atoms()
         desc = ("water: 3000 molecules as O(13),H(5),H(5) atom blocks (N=69000), 5 A cutoff, "
                 "U[-1,1]*exp(-0.5 d), beta=0, no filter")
+    elif name == "semi_empirical":
+        w = W.semi_empirical()
+        desc = ("semi_empirical: 186,624 molecules as 6x6 blocks (N=1,119,744), 8.7 A cutoff (0.05% occupancy), "
+                "U[-1,1]*exp(-0.5 d), beta=0, filter_eps=0.07")
+    elif name == "mixed_dense":
+        w = W.mixed_dense()
+        desc = ("mixed_dense: 64x64 blocks with edges cycling 9,22,32 (N=1332), fully occupied, U[-1,1], "
+                "beta=1, no filter")
     else:
         raise SystemExit(f"unknown workload {name}")
     return w, desc
+
+
+SWEEP_EDGES = (4, 5, 6, 8, 9, 12, 13, 16, 20, 22, 23, 24, 26, 32, 40, 45, 48, 55, 64, 78)
+
+
+def sweep_leg(steps, warmup, working_set=2 << 30):
+    """Streaming block products C_i += A_i B_i with m = n = k = s for each
+    edge s, the operands of one multiply about `working_set` bytes; returns
+    per-edge rates and their geometric mean."""
+    import torch
+    from paper_1708_03604_amd import bsmm
+    from paper_1708_03604_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    rows = []
+    for s in SWEEP_EDGES:
+        nblocks = max(1, working_set // (8 * 4 * s * s))
+        w = W.block_stream(8000 + s, s, s, s, nblocks)
+        dA, dB, dCin = (bsmm.Matrix.from_csr(x, stream) for x in (w.A, w.B, w.C_old))
+        dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
+        for _ in range(warmup):
+            bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC, 0.0, stream=stream)
+        torch.cuda.synchronize()
+        bsmm.bsmm_timing(dC.handle, 1)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC, 0.0, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ph, n = bsmm.bsmm_phase_times(dC.handle)
+        st = bsmm.bsmm_stats(dC.handle)
+        num_ms = ph["numeric"] / max(n, 1)
+        flops = st["useful_flops"]
+        row = {"edge": s, "blocks": nblocks, "path": PATH_NAMES.get(st["path"], st["path"]),
+               "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
+               "numeric_ms": round(num_ms, 4), "numeric_gflops": round(flops / num_ms / 1e6, 1),
+               "numeric_gbs": round(8 * 4 * s * s * nblocks / num_ms / 1e6, 1)}
+        log(f"[sweep] {row}")
+        rows.append(row)
+        for m in (dA, dB, dCin, dC):
+            m.close()
+        del w
+    gm = math.exp(sum(math.log(r["gflops"]) for r in rows) / len(rows))
+    return gm, rows
+
+
+PATH_NAMES = {0: "generic", 1: "tile23", 2: "small", 3: "split23"}
 
 
 def take_rows(M, rows):
@@ -233,6 +288,19 @@ def main():
         log(f"[bench] chain: {ch['ms_per_chain']} ms, {out['value']} GFLOP/s, residual {ch['residual_fro']:.3e}")
         print(json.dumps(out), flush=True)
         return
+    if args.workload == "sweep":
+        torch.cuda.set_device(0)
+        gm, rows = sweep_leg(args.steps, args.warmup)
+        out = {"metric": "geometric mean of useful GFLOP/s of streaming block products C_i += A_i B_i "
+                         "(m=n=k=s), FP64",
+               "value": round(gm, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": round(sum(r["ms"] for r in rows), 4),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"block_stream sweep, s in {list(SWEEP_EDGES)}, 2 GiB of operands per s"},
+               "sweep": rows}
+        print(json.dumps(out), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"[bench] building workload {args.workload}")
@@ -286,7 +354,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "prec": "fp64", "products": stats["products"],
-                   "result_blocks": stats["nnzb"], "useful_gflop_per_step": round(flops / 1e9, 4)},
+                   "result_blocks": stats["nnzb"], "useful_gflop_per_step": round(flops / 1e9, 4),
+                   "kernel_path": PATH_NAMES.get(stats["path"], stats["path"])},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic() if args.workload == "molecules" else None,

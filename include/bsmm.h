@@ -64,7 +64,7 @@ enum { BSMM_PTR_HOST = 0, BSMM_PTR_DEVICE = 1 };
 
 /* Kernel path that computed the block products of a multiply. */
 enum {
-  BSMM_PATH_GENERIC = 0, /* any block sizes, FP64 */
+  BSMM_PATH_GENERIC = 0, /* any other block sizes, FP64, in 32x32 sub-tiles and K chunks of 32 */
   BSMM_PATH_TILE23 = 1,  /* uniform 23x23 blocks, FP64 */
   BSMM_PATH_SMALL = 2,   /* every block edge <= 16, FP64, one launch over all shape classes */
   BSMM_PATH_SPLIT23 = 3  /* uniform 23x23 blocks, BSMM_SPLIT_BF16X3 */

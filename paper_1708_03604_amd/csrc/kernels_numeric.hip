@@ -11,41 +11,181 @@
 
 namespace bsmm {
 
-// Any block sizes: lanes own output elements, operands read from global memory.
-__global__ __launch_bounds__(256) void k_numeric_generic(NumArgs g) {
-  const int lane = threadIdx.x & 63;
-  const int32_t nwaves = gridDim.x * 4;
+// ---------------------------------------------------------------------------
+// Any block sizes (the path for blocks that are neither all <= 16 nor all
+// 23x23): one wave per C block at a time.  The C block is cut into 32x32
+// sub-tiles and every product into K chunks of at most 32; a sub-tile is
+// accumulated in registers over all chunks of all products of its C block.
+//
+// Lane l = 8*ty + tx owns sub-tile rows 4ty..4ty+3 and columns 4tx..4tx+3.
+// A chunk is staged through wave-private LDS: A transposed (row t holds
+// A(r, k0+t) for the sub-tile's rows) and B as is, both with a row stride of
+// kMidStride doubles, so a lane reads its 4 A values and 4 B values of inner
+// index t with two 16-byte loads each.  The loads of the next chunk are
+// issued before the current chunk is multiplied.  Rows and columns past the
+// block stay stale in LDS; the outputs they feed are never stored.
+// ---------------------------------------------------------------------------
+constexpr int kMid = 32;
+constexpr int kMidStride = 34;  // doubles per LDS row: 16-byte aligned rows, 2-way write conflicts at most
+constexpr int kMidOperand = kMid * kMidStride;
+
+// Position of a wave in its chunk sequence: C block c, sub-tile (ti, tj),
+// product x in [x0, x1), K chunk k0 of the product's inner size k.
+struct MidCursor {
+  int32_t c, m, n, ti, tj, nti, ntj, k, k0;
+  int64_t x, x0, x1, aoff, boff;
+  bool valid;
+};
+
+__device__ __forceinline__ void mid_product(const NumArgs& g, MidCursor& u) {
+  if (u.x < u.x1) {
+    const int32_t a = g.prod_a[u.x];
+    const int64_t a0 = g.A.blk_off[a], a1 = g.A.blk_off[a + 1];
+    u.aoff = a0;
+    u.boff = g.B.blk_off[g.prod_b[u.x]];
+    u.k = (int32_t)((uint32_t)(a1 - a0) / (uint32_t)u.m);
+  } else {
+    u.k = 0;  // C block without products: one empty chunk finishes each sub-tile
+  }
+  u.k0 = 0;
+}
+
+__device__ __forceinline__ void mid_block(const NumArgs& g, MidCursor& u, int32_t nnzc) {
+  u.valid = u.c < nnzc;
+  if (!u.valid) return;
+  const int64_t off = g.c_blk_off[u.c];
+  u.n = g.c_col_sizes[g.c_col_idx[u.c]];
+  u.m = (int32_t)((uint32_t)(g.c_blk_off[u.c + 1] - off) / (uint32_t)u.n);
+  u.nti = (u.m + kMid - 1) / kMid;
+  u.ntj = (u.n + kMid - 1) / kMid;
+  u.ti = 0;
+  u.tj = 0;
+  u.x0 = g.prod_ptr[u.c];
+  u.x1 = g.prod_ptr[u.c + 1];
+  u.x = u.x0;
+  mid_product(g, u);
+}
+
+// Advance to the next chunk; returns true if the chunk just left was the
+// last one of its sub-tile.
+__device__ __forceinline__ bool mid_next(const NumArgs& g, MidCursor& u, int32_t nnzc, int32_t nwaves) {
+  u.k0 += kMid;
+  if (u.k0 < u.k) return false;
+  if (u.x < u.x1) ++u.x;
+  if (u.x < u.x1) {
+    mid_product(g, u);
+    return false;
+  }
+  if (++u.tj == u.ntj) {
+    u.tj = 0;
+    ++u.ti;
+  }
+  if (u.ti < u.nti) {
+    u.x = u.x0;
+    mid_product(g, u);
+    return true;
+  }
+  u.c += nwaves;
+  mid_block(g, u, nnzc);
+  return true;
+}
+
+__global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
+  __shared__ __align__(16) double lds[4][2 * kMidOperand];  // per wave: A^T, then B
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ty = lane >> 3, tx = lane & 7;
+  const int lc = lane & 31, lr = lane >> 5;  // staging: column lc of rows lr, lr+2, ..., lr+30
+  double* const As = &lds[wv][0];
+  double* const Bs = &lds[wv][kMidOperand];
   const int32_t nnzc = live_nnzc(g.totals);
-  for (int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < nnzc; c += nwaves) {
-    const int32_t n = g.c_col_sizes[g.c_col_idx[c]];
-    const int64_t off = g.c_blk_off[c];
-    const int64_t mn = g.c_blk_off[c + 1] - off;
-    const int32_t m = (int32_t)(mn / n);
-    const int64_t p0 = g.prod_ptr[c], p1 = g.prod_ptr[c + 1];
-    const int32_t old = g.use_old ? g.c_old_idx[c] : -1;
-    const double* oldv = old >= 0 ? g.Cin.values + g.Cin.blk_off[old] : nullptr;
-    for (int64_t e0 = 0; e0 < mn; e0 += 64) {
-      const int64_t e = e0 + lane;
-      const bool active = e < mn;
-      const int32_t r = active ? (int32_t)(e / n) : 0;
-      const int32_t s = active ? (int32_t)(e % n) : 0;
-      double acc = 0.0;
-      for (int64_t x = p0; x < p1; ++x) {
-        const int32_t a = g.prod_a[x];
-        const int32_t b = g.prod_b[x];
-        const int64_t ao = g.A.blk_off[a];
-        const int32_t k = (int32_t)((g.A.blk_off[a + 1] - ao) / m);
-        const double* av = g.A.values + ao + (int64_t)r * k;
-        const double* bv = g.B.values + g.B.blk_off[b] + s;
-        if (active)
-          for (int32_t t = 0; t < k; ++t) acc = fma(av[t], bv[(int64_t)t * n], acc);
-      }
-      if (active) {
-        double v = g.alpha * acc;
-        if (oldv) v = v + g.beta * oldv[e];
-        g.c_values[off + e] = v;
+  const int32_t nwaves = gridDim.x * 4;
+
+  MidCursor f;  // fetch cursor, one chunk ahead of the compute cursor
+  f.c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+  mid_block(g, f, nnzc);
+  if (!f.valid) return;
+
+  // Operand registers of the chunk in flight: A(32ti + lr + 2v, k0 + lc) and
+  // B(k0 + lr + 2v, 32tj + lc), zero outside the block and the chunk.
+  double ra[16], rb[16];
+  auto fetch = [&](const MidCursor& u) {
+    const int kk = min(kMid, u.k - u.k0);
+    const int mm = min(kMid, u.m - kMid * u.ti), nn = min(kMid, u.n - kMid * u.tj);
+    const double* ap = g.A.values + u.aoff + (int64_t)(kMid * u.ti + lr) * u.k + u.k0 + lc;
+    const double* bp = g.B.values + u.boff + (int64_t)(u.k0 + lr) * u.n + kMid * u.tj + lc;
+    const bool acol = lc < kk, bcol = lc < nn;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = lr + 2 * v;
+      ra[v] = (acol && r < mm) ? ap[(int64_t)2 * v * u.k] : 0.0;
+      rb[v] = (bcol && r < kk) ? bp[(int64_t)2 * v * u.n] : 0.0;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      As[lc * kMidStride + lr + 2 * v] = ra[v];
+      Bs[(lr + 2 * v) * kMidStride + lc] = rb[v];
+    }
+  };
+  auto sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  fetch(f);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (;;) {
+    // the chunk to multiply now is the one the fetch cursor points at
+    const MidCursor cur = f;
+    sync();
+    stage();
+    sync();
+    const bool last = mid_next(g, f, nnzc, nwaves);
+    if (f.valid) fetch(f);
+    const int kk = max(0, min(kMid, cur.k - cur.k0));
+    const double* ap = As + 4 * ty;
+    const double* bp = Bs + 4 * tx;
+#pragma unroll 4
+    for (int t = 0; t < kk; ++t) {
+      const double2 a01 = *reinterpret_cast<const double2*>(ap + t * kMidStride);
+      const double2 a23 = *reinterpret_cast<const double2*>(ap + t * kMidStride + 2);
+      const double2 b01 = *reinterpret_cast<const double2*>(bp + t * kMidStride);
+      const double2 b23 = *reinterpret_cast<const double2*>(bp + t * kMidStride + 2);
+      const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+      const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    if (last) {
+      // alpha * acc + beta * C_in, then store the lane's 4x4 outputs
+      const int64_t off = g.c_blk_off[cur.c];
+      const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
+      const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = kMid * cur.ti + 4 * ty + i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int cc = kMid * cur.tj + 4 * tx + j;
+          if (r < cur.m && cc < cur.n) {
+            const int64_t e = (int64_t)r * cur.n + cc;
+            double v = g.alpha * acc[i][j];
+            if (ov) v = v + g.beta * ov[e];
+            g.c_values[off + e] = v;
+          }
+          acc[i][j] = 0.0;
+        }
       }
     }
+    if (!f.valid) break;
   }
 }
 
@@ -359,9 +499,11 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
                        a.c_values, a.totals, a.use_old, a.alpha, a.beta);
     return hipGetLastError();
   }
-  int64_t blocks = (a.nnzc_bound + 3) / 4;
-  if (blocks > 32768) blocks = 32768;
-  hipLaunchKernelGGL(k_numeric_generic, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int64_t blocks = (a.nnzc_bound + 3) / 4;  // every wave owns at least one C block at the start
+  if (blocks > 2 * cus) blocks = 2 * cus;   // two workgroups of 4 waves per CU stay resident
+  hipLaunchKernelGGL(k_numeric_mid, dim3((uint32_t)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

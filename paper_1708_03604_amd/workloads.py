@@ -299,3 +299,62 @@ def identity_like(M, scale=1.0):
     blocks = [scale * np.eye(int(s)).ravel() for s in M.row_sizes]
     vals = np.concatenate(blocks) if blocks else np.zeros(0)
     return with_pattern(M.row_sizes, M.col_sizes, rp, ci, vals)
+
+
+def semi_empirical(seed=6000, nmol=186624, density=0.0334, cutoff=8.7, bs=6, eps=0.07):
+    """S-E-shaped input (Section 3.2, Table 1: 6x6 blocks, 186,624 water
+    molecules, occupancy about 0.05%): one 6x6 block per molecule, centres
+    uniform in an open cube at liquid-water density; block (i,j) present iff
+    the centres are closer than ``cutoff`` (8.7 A gives 0.05% occupancy at
+    this size); values U[-1,1]*exp(-0.5*d); beta = 0; the on-the-fly filter
+    at ``eps`` keeps about 1,300 products per block row, so the product has a
+    pattern about as sparse as its operands.  Positions come from seed +100,
+    values of A and B from seeds +0 and +1."""
+    L = box_side(nmol, density)
+    pos = np.random.default_rng(seed + 100).uniform(0.0, L, (nmol, 3))
+    ii, jj, dd = cutoff_pairs(pos, cutoff)
+    rp, ci, dd = _csr_with_block_scalars(nmol, ii, jj, dd)
+    del ii, jj
+    sizes = np.full(nmol, bs, dtype=np.int32)
+    decay = np.exp(-0.5 * dd)
+    mats = []
+    for off in (0, 1):
+        v = np.random.default_rng(seed + off).uniform(-1.0, 1.0, len(ci) * bs * bs)
+        v.reshape(len(ci), bs * bs)[:] *= decay[:, None]
+        mats.append(with_pattern(sizes, sizes, rp, ci, v))
+    A, B = mats
+    return Workload(f"semi_empirical{nmol}_b{bs}_cut{cutoff}_eps{eps}", A, B, None, 1.0, 0.0, eps,
+                    {"N": int(nmol * bs), "box": L})
+
+
+def mixed_dense(seed=7000, nb=64, sizes=(9, 22, 32)):
+    """H2O-64-shaped input (Section 3.1: block sizes combining 9, 22 and 32,
+    fully occupied matrices): nb x nb blocks, every block present, block
+    edges cycling through ``sizes``; values U[-1,1]; C = A*B + C_old with a
+    fully occupied C_old (seeds +0, +1, +2), no filtering."""
+    edges = np.resize(np.asarray(sizes, dtype=np.int32), nb)
+    full = np.ones((nb, nb), dtype=bool)
+    rp, ci = pattern_from_mask(full)
+    mats = []
+    for off in (0, 1, 2):
+        M = with_pattern(edges, edges, rp, ci)
+        M.values = values_uniform(seed + off, M.block_elems())
+        mats.append(M)
+    A, B, C = mats
+    return Workload(f"mixed_dense{nb}_b{'_'.join(map(str, sizes))}", A, B, C, 1.0, 1.0, 0.0,
+                    {"N": int(edges.sum())})
+
+
+def block_stream(seed, m, n, k, nblocks):
+    """Independent block products C_i += A_i B_i, i < nblocks, as a
+    block-diagonal multiply (the streaming micro-benchmark of Section 2 /
+    Figure 1): A has m x k blocks, B k x n, C_old m x n on the diagonal;
+    values U[-1,1] (seeds +0, +1, +2); beta = 1, no filtering."""
+    rp = np.arange(nblocks + 1, dtype=np.int32)
+    ci = np.arange(nblocks, dtype=np.int32)
+    rs, ks, cs = (np.full(nblocks, x, dtype=np.int32) for x in (m, k, n))
+    A = with_pattern(rs, ks, rp, ci, values_uniform(seed, np.full(nblocks, m * k)))
+    B = with_pattern(ks, cs, rp, ci, values_uniform(seed + 1, np.full(nblocks, k * n)))
+    C = with_pattern(rs, cs, rp, ci, values_uniform(seed + 2, np.full(nblocks, m * n)))
+    return Workload(f"block_stream_m{m}_n{n}_k{k}_x{nblocks}", A, B, C, 1.0, 1.0, 0.0,
+                    {"N": int(nblocks * max(m, n, k))})
