@@ -145,6 +145,11 @@ __device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA& ra, i
 
 // ------------------------------------------------------------------ count
 
+// Candidates a thread takes at a time in the row passes: their index and
+// norm loads are issued together, so a workgroup keeps several gathers in
+// flight per thread (rows of thousands of candidates are latency-bound).
+constexpr int kCandBatch = 4;
+
 __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
   __shared__ int32_t hkey[kHashSlots];
   __shared__ RowA ra;
@@ -180,20 +185,33 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
     }
     uint32_t np = 0;
     uint64_t nf = 0;
-    for (int32_t t = tid; t < T; t += kSymThreads) {
-      int32_t p, q;
-      candidate(ra, nA, t, &p, &q);
-      if (!keep_product(g, ra, p, q)) continue;
-      ++np;
-      const int32_t j = g.B.col_idx[q];
-      nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[p];
-      bool fresh;
-      const int h = hash_insert(hkey, j, &fresh);
-      if (h < 0) {
-        s_bad = 1;
-      } else if (fresh) {
-        atomicAdd(&s_nc, 1);
-        atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+    // kCandBatch candidates per thread at a time, their global loads issued together
+    for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
+      int32_t pp[kCandBatch], jj[kCandBatch];
+      bool kk[kCandBatch];
+#pragma unroll
+      for (int u = 0; u < kCandBatch; ++u) {
+        const int32_t t = tb + u * kSymThreads;
+        int32_t p = 0, q = 0;
+        if (t < T) candidate(ra, nA, t, &p, &q);
+        pp[u] = p;
+        kk[u] = t < T && keep_product(g, ra, p, q);
+        jj[u] = t < T ? g.B.col_idx[q] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCandBatch; ++u) {
+        if (!kk[u]) continue;
+        ++np;
+        const int32_t j = jj[u];
+        nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[pp[u]];
+        bool fresh;
+        const int h = hash_insert(hkey, j, &fresh);
+        if (h < 0) {
+          s_bad = 1;
+        } else if (fresh) {
+          atomicAdd(&s_nc, 1);
+          atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+        }
       }
     }
     if (g.use_old) {
@@ -298,9 +316,8 @@ __device__ __forceinline__ bool fill_keep(const SymArgs& g, const RowFill& ra, i
 // One workgroup per C block row.  After the hash has merged the kept
 // candidates by column, the columns are ranked (sorted pattern), the counts
 // scanned (each C block's slice of the stack), and the products placed in
-// ascending A entry order, i.e. ascending k: in one pass per A entry p the
-// candidates of p have distinct columns, so each C block receives at most one
-// product per pass and a plain LDS cursor per block suffices.
+// ascending A entry order, i.e. ascending k (the candidates of one A entry
+// have distinct columns, so within a C block the entries order its products).
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
   __shared__ int32_t hkey[kHashSlots];
   __shared__ int32_t hcnt[kHashSlots];  // product count per slot, then the slot's rank
@@ -328,16 +345,28 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     const int32_t T = load_row_fill(g, i, ra, &a0, &nA);
     if (T < 0) continue;  // uniform over the workgroup; reported by the count pass
     const bool one_chunk = T <= kCandCache;
-    for (int32_t t = tid; t < T; t += kSymThreads) {
-      const int32_t p = fill_entry_of(ra, nA, t);
-      const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-      int h = -1;
-      if (fill_keep(g, ra, p, q)) {
-        bool fresh;
-        h = hash_insert(hkey, g.B.col_idx[q], &fresh);
-        if (h >= 0) atomicAdd(&hcnt[h], 1);
+    for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
+      int32_t jj[kCandBatch];
+      bool kk[kCandBatch];
+#pragma unroll
+      for (int u = 0; u < kCandBatch; ++u) {
+        const int32_t t = tb + u * kSymThreads;
+        const int32_t p = t < T ? fill_entry_of(ra, nA, t) : 0;
+        const int32_t q = ra.qs[p] + (t - ra.pre[p]);
+        kk[u] = t < T && fill_keep(g, ra, p, q);
+        jj[u] = t < T ? g.B.col_idx[q] : 0;
       }
-      if (one_chunk) cslot[t] = (int16_t)h;
+#pragma unroll
+      for (int u = 0; u < kCandBatch; ++u) {
+        const int32_t t = tb + u * kSymThreads;
+        int h = -1;
+        if (kk[u]) {
+          bool fresh;
+          h = hash_insert(hkey, jj[u], &fresh);
+          if (h >= 0) atomicAdd(&hcnt[h], 1);
+        }
+        if (one_chunk && t < T) cslot[t] = (int16_t)h;
+      }
     }
     if (g.use_old) {
       const int32_t o1 = g.Cin.row_ptr[i + 1];
@@ -407,29 +436,66 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
         rv += vs[u];
       }
     }
+    // svs is free after the scan: it holds the round masks of the placement
+    uint32_t* const rmask = reinterpret_cast<uint32_t*>(svs);
+    for (int r = tid; r < nC; r += kSymThreads) rmask[r] = 0;
     __syncthreads();
     const int64_t prow = g.row_pstart[i];
     for (int32_t t0 = 0; t0 < T; t0 += kCandCache) {
       const int32_t t1 = T - t0 > kCandCache ? t0 + kCandCache : T;
       if (!one_chunk) {
-        for (int32_t t = t0 + tid; t < t1; t += kSymThreads) {
-          const int32_t p = fill_entry_of(ra, nA, t);
-          const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-          cslot[t - t0] = (int16_t)(fill_keep(g, ra, p, q) ? hash_find(hkey, g.B.col_idx[q]) : -1);
+        for (int32_t tb = t0 + tid; tb < t1; tb += kCandBatch * kSymThreads) {
+          int32_t jj[kCandBatch];
+          bool kk[kCandBatch];
+#pragma unroll
+          for (int u = 0; u < kCandBatch; ++u) {
+            const int32_t t = tb + u * kSymThreads;
+            const int32_t p = t < t1 ? fill_entry_of(ra, nA, t) : 0;
+            const int32_t q = ra.qs[p] + (t - ra.pre[p]);
+            kk[u] = t < t1 && fill_keep(g, ra, p, q);
+            jj[u] = t < t1 ? g.B.col_idx[q] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < kCandBatch; ++u) {
+            const int32_t t = tb + u * kSymThreads;
+            if (t < t1) cslot[t - t0] = (int16_t)(kk[u] ? hash_find(hkey, jj[u]) : -1);
+          }
         }
         __syncthreads();
       }
-      for (int32_t p = fill_entry_of(ra, nA, t0); p < nA && ra.pre[p] < t1; ++p) {
-        const int32_t u0 = ra.pre[p] > t0 ? ra.pre[p] : t0;
-        const int32_t u1 = ra.pre[p + 1] < t1 ? ra.pre[p + 1] : t1;
-        for (int32_t t = u0 + tid; t < u1; t += kSymThreads) {
+      // Place the chunk's kept candidates in rounds of 32 A entries: mark
+      // which entries of the round reach each C block (one bit per entry),
+      // then a candidate's place is its block's cursor plus the number of
+      // earlier entries of the round that reach the same block, and the
+      // cursors advance by the round's counts.  A round needs three barriers
+      // however many entries it holds.
+      const int32_t pl = fill_entry_of(ra, nA, t1 - 1);
+      for (int32_t r0 = fill_entry_of(ra, nA, t0); r0 <= pl; r0 += 32) {
+        const int32_t r1 = r0 + 32 <= pl + 1 ? r0 + 32 : pl + 1;
+        const int32_t tb = ra.pre[r0] > t0 ? ra.pre[r0] : t0;
+        const int32_t te = ra.pre[r1] < t1 ? ra.pre[r1] : t1;
+        for (int32_t t = tb + tid; t < te; t += kSymThreads) {
+          const int h = cslot[t - t0];
+          if (h >= 0) atomicOr(&rmask[hcnt[h]], 1u << (fill_entry_of(ra, nA, t) - r0));
+        }
+        __syncthreads();
+        for (int32_t t = tb + tid; t < te; t += kSymThreads) {
           const int h = cslot[t - t0];
           if (h >= 0) {
             const int r = hcnt[h];
-            const int32_t pos = spre[r] + cursor[r];
-            cursor[r] = cursor[r] + 1;
+            const int32_t p = fill_entry_of(ra, nA, t);
+            const uint32_t below = rmask[r] & ((1u << (p - r0)) - 1u);
+            const int32_t pos = spre[r] + cursor[r] + __builtin_popcount(below);
             g.prod_a[prow + pos] = a0 + p;
             g.prod_b[prow + pos] = ra.qs[p] + (t - ra.pre[p]);
+          }
+        }
+        __syncthreads();
+        for (int r = tid; r < nC; r += kSymThreads) {
+          const uint32_t mk = rmask[r];
+          if (mk) {
+            cursor[r] += __builtin_popcount(mk);
+            rmask[r] = 0;
           }
         }
         __syncthreads();
