@@ -171,6 +171,40 @@ def cpu_baseline(w, gpu_flops_per_step, target_s=12.0):
             "seconds": dt}
 
 
+def small_class_leg(w, dA, dB, dCin, dC, stream, reps=5):
+    """Per shape class (and per (m, n, k) triple) breakdown of the small-block
+    path: the tuner times each class alone with every pipeline variant; the
+    class's useful flops come from the exported product stack.  Leaves C as
+    the plain multiply computes it."""
+    from paper_1708_03604_amd import bsmm
+    v, ms = bsmm.bsmm_tune_small(w.alpha, dA.handle, dB.handle, w.beta, dCin.handle if dCin is not None else None,
+                                 dC.handle, w.eps, reps, stream)
+    if v < 0:
+        return None
+    st = dC.stack(stream)
+    rp, ci, _ = dC.to_host(stream)
+    crow = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    m = w.A.row_sizes[crow[st[:, 0]]].astype(np.int64)
+    n = w.B.col_sizes[ci[st[:, 0]]].astype(np.int64)
+    k = w.A.col_sizes[w.A.col_idx[st[:, 1]]].astype(np.int64)
+    cls = (m > 8).astype(np.int64) * 2 + (n > 8).astype(np.int64)
+    names = ("8x8", "8x16", "16x8", "16x16")
+    classes = []
+    for c in range(4):
+        sel = cls == c
+        fl = float(np.sum(2 * m[sel] * n[sel] * k[sel]))
+        t = ms[v, c] / reps
+        triples = {}
+        for mm, nn, kk in set(zip(m[sel].tolist(), n[sel].tolist(), k[sel].tolist())):
+            s2 = sel & (m == mm) & (n == nn) & (k == kk)
+            triples[f"{mm}x{nn}x{kk}"] = {"products": int(s2.sum()), "gflop": round(2 * mm * nn * kk * int(s2.sum()) / 1e9, 4)}
+        classes.append({"class": names[c], "products": int(sel.sum()), "gflop": round(fl / 1e9, 4),
+                        "ms": round(t, 4), "gflops": round(fl / t / 1e6, 1) if t > 0 else None,
+                        "triples": dict(sorted(triples.items()))})
+    return {"variant": int(v), "depths": bsmm.bsmm_small_variant(v), "note": "each class timed alone (launch of "
+            "the whole grid over that class's list), mean of the tuner's launches", "classes": classes}
+
+
 def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_ms):
     """Same multiply with the operands split into three BF16 terms on matrix
     cores; error against the FP64 result (which matches the oracle within
@@ -370,6 +404,11 @@ def main():
         sp = out["split_bf16x3"]
         log(f"[bench] split: {sp['ms_per_step']} ms/step ({sp['speedup_vs_fp64']}x), rel Frobenius error "
             f"{sp['rel_frobenius_vs_fp64']:.2e}")
+    if args.workload == "water":
+        log("[bench] per shape class timing of the small-block kernel")
+        out["small_classes"] = small_class_leg(w, dA, dB, dCin, dC, stream)
+        for c in out["small_classes"]["classes"]:
+            log(f"[bench]   class {c['class']}: {c['products']} products, {c['ms']} ms, {c['gflops']} GFLOP/s")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, flops)
