@@ -66,3 +66,43 @@ def test_random_matrix_int_values():
     M = W.random_matrix(3, [5, 13], [13, 5, 23], 0.7, kind="int")
     assert np.all(M.values == np.round(M.values)) and np.all(np.abs(M.values) <= 4)
     assert len(M.values) == M.nvals
+
+
+def test_semi_empirical_shape():
+    # full size is 186,624 molecules; a smaller box at the same density keeps this fast
+    w = W.semi_empirical(nmol=12000)
+    A = w.A
+    assert A.nbrows == 12000 and np.all(A.row_sizes == 6) and w.info["N"] == 72000
+    per_row = np.diff(A.row_ptr)
+    # 8.7 A cutoff at 0.0334 / A^3: 92 neighbours in the bulk (0.05% of 186,624)
+    L = w.info["box"]
+    assert 60 < per_row.mean() < 92
+    m = np.zeros((12000, 12000), dtype=bool)
+    m[A.block_rows(), A.col_idx] = True
+    assert np.array_equal(m, m.T) and m.diagonal().all()
+    assert np.array_equal(w.B.col_idx, A.col_idx) and not np.array_equal(w.A.values, w.B.values)
+    assert w.C_old is None and w.beta == 0.0 and w.eps == 0.07
+    assert abs(L - (12000 / 0.0334) ** (1 / 3)) < 1e-9
+    assert np.all(np.abs(A.values) <= 1.0)
+    _same(A, W.semi_empirical(nmol=12000).A)
+
+
+def test_mixed_dense_shape():
+    w = W.mixed_dense()
+    A = w.A
+    assert A.nbrows == 64 and A.nnzb == 64 * 64 and w.info["N"] == 1332
+    assert list(A.row_sizes[:6]) == [9, 22, 32, 9, 22, 32]
+    assert np.array_equal(A.row_sizes, A.col_sizes)
+    assert A.nvals == 1332 * 1332 and w.C_old.nnzb == 64 * 64
+    assert w.beta == 1.0 and w.eps == 0.0
+    _same(A, W.mixed_dense().A)
+
+
+def test_block_stream_shape():
+    w = W.block_stream(8005, 5, 7, 3, 11)
+    assert w.A.nnzb == w.B.nnzb == w.C_old.nnzb == 11
+    assert np.array_equal(w.A.col_idx, np.arange(11)) and np.array_equal(w.A.row_ptr, np.arange(12))
+    assert np.all(w.A.row_sizes == 5) and np.all(w.A.col_sizes == 3)
+    assert np.all(w.B.row_sizes == 3) and np.all(w.B.col_sizes == 7)
+    assert w.A.nvals == 11 * 15 and w.B.nvals == 11 * 21 and w.C_old.nvals == 11 * 35
+    assert w.beta == 1.0 and w.alpha == 1.0
