@@ -449,7 +449,7 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   // (reads past 4*ceil(k/4) stay inside the stage and are not used).
   auto compute = [&](auto stage) {
     constexpr int st = decltype(stage)::value;
-    constexpr int G = RM + RN <= 4 ? 4 : 2;
+    constexpr int G = RM + RN <= 4 ? 2 : 1;
     const int32_t w = stw[st];
     const int32_t n = (w >> 5) & 31, k = (w >> 10) & 31;
     const double* As = wl + st * kStage + rho * RM * k + s;
@@ -565,10 +565,276 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   }
 }
 
+// Class 0 (C blocks of at most 8 x 8): four products of one C block per step,
+// one per group of 16 lanes.  Group g = lane >> 4 takes the step's g-th
+// product; its lanes own the same 2x2 outputs as in the K-slice layout of the
+// other classes (rows 2rho, 2rho+1, columns 2gam, 2gam+1), over every inner
+// index t < k, and the four groups' sums are added at the end of the C block
+// exactly as the K slices are.  A step holds the next one to four products of
+// the current C block (a C block's last step may leave groups without a
+// product: their k is 0 and their B block is all zeros).  Against one product
+// per step over four K slices this quarters the per-product instructions,
+// which bound the small-block kernel, at the cost of 4 FMA per 4 LDS reads.
+//
+// One LDS stage (each group: A, then B, 128 doubles each; the tile of a
+// finished block is parked there too) and D register slots of four products.
+template <int D>
+__device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
+                                           int32_t xcd, int32_t wpx, int32_t wix, int lane) {
+  constexpr int MP = 8, NP = 8, RM = 2, RN = 2, V = 4;
+  constexpr int QA = 8, QB = 8;  // loads per lane of a group: A, B blocks of at most 128 elements
+  constexpr int kGroup = 256;    // LDS doubles per group: A (128), then B (128)
+  const int s = lane >> 4, rho = (lane >> 2) & 3, gam = lane & 3;  // s: the lane's group
+  const int li = lane & 15;
+
+  // This wave's run of the list: [E0, E1), products [Q0, Q0 + NQ) in list order.
+  const int64_t L = L1 - L0;
+  const int64_t X0 = L0 + L * xcd / kXcds, X1 = L0 + L * (xcd + 1) / kXcds;
+  const int32_t E0 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix));
+  const int32_t E1 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix + 1));
+  if (E0 >= E1) return;
+  const int64_t Q0 = P.qstart[E0];
+  const int32_t NQ = (int32_t)(P.qstart[E1] - Q0);
+  const int4* __restrict__ dq = P.desc + Q0;
+
+  // ---- entry batches: lane u holds entry eb + u (current) and eb + 64 + u (next)
+  int32_t eb = E0, ei = E0;
+  int4 ca, cb, na, nb;
+  auto load_entries = [&](int32_t base, int4& x, int4& y) {
+    const int64_t e = base + lane < E1 ? base + lane : E1 - 1;
+    x = P.list[2 * e];
+    y = P.list[2 * e + 1];
+  };
+  load_entries(eb, ca, cb);
+  settle(ca);
+  settle(cb);
+  load_entries(eb + 64, na, nb);
+  // ---- descriptor batches: lane u holds descriptor qb + u (current) and qb + 64 + u (next)
+  int32_t qb = 0, qi = 0;
+  int4 cd, nd;
+  auto load_desc = [&](int32_t base, int4& x) {
+    const int32_t q = base + lane < NQ ? base + lane : (NQ > 0 ? NQ - 1 : 0);
+    x = dq[q];
+  };
+  load_desc(qb, cd);
+  settle(cd);
+  load_desc(qb + 64, nd);
+
+  // ---- finishing data of the C blocks between fetch and finish: a queue in
+  // lanes (entry w at lane w mod 64; at most D+1 blocks are open at a time)
+  int32_t fifo_mn = 0, fifo_co0 = 0, fifo_co1 = 0, fifo_oo0 = 0, fifo_oo1 = 0;
+  int32_t fw = 0, fr = 0;
+
+  // ---- fetch cursor: current entry (m, n, products left)
+  bool fok = true;
+  int32_t fm = 0, fn = 0, frem = 0;
+  auto take_entry = [&]() {
+    const int u = ei - eb;
+    const int32_t mn = __builtin_amdgcn_readlane(ca.x, u);
+    fm = mn & 255;
+    fn = mn >> 8;
+    frem = __builtin_amdgcn_readlane(ca.z, u);
+    const bool mine = lane == (fw & 63);
+    fifo_mn = mine ? mn : fifo_mn;
+    fifo_co0 = mine ? __builtin_amdgcn_readlane(cb.x, u) : fifo_co0;
+    fifo_co1 = mine ? __builtin_amdgcn_readlane(cb.y, u) : fifo_co1;
+    fifo_oo0 = mine ? __builtin_amdgcn_readlane(cb.z, u) : fifo_oo0;
+    fifo_oo1 = mine ? __builtin_amdgcn_readlane(cb.w, u) : fifo_oo1;
+    ++fw;
+  };
+  auto next_entry = [&]() {
+    ++ei;
+    if (ei >= E1) {
+      fok = false;
+      return;
+    }
+    if (ei - eb == 64) {
+      eb += 64;
+      ca = na;
+      cb = nb;
+      settle(ca);
+      settle(cb);
+      load_entries(eb + 64, na, nb);
+    }
+    take_entry();
+  };
+  take_entry();
+
+  // ---- slots: step X lives in slot X % D from its fetch to its stage write.
+  // Packed word: m | n << 5 | kmax << 10 | valid << 15 | last << 16, where
+  // kmax is the largest inner size of the step's products; sk holds the
+  // inner size of the lane's group (0: no product).
+  double sa[D][QA], sb[D][QB];
+  int32_t sw[D], sk[D];
+  // masked-off lanes keep their previous values: start from zeros so that
+  // every stale value is finite (inner steps past k multiply them by zero)
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j < QA; ++j) sa[d][j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) sb[d][j] = 0.0;
+  }
+  auto fetch = [&](auto slot) {
+    constexpr int d = decltype(slot)::value;
+    int64_t ao = 0, bo = 0;
+    int32_t k = 0, kmax = 0;
+    if (fok && frem > 0) {
+      const int32_t cnt = frem < 4 ? frem : 4;
+      const int u0 = qi - qb;
+      // descriptors u0 .. u0+cnt-1 of the current batch; past 63 they are
+      // the first ones of the next batch
+      static_for<0, 4>([&](auto gi) {
+        constexpr int G = decltype(gi)::value;
+        if (G < cnt) {
+          const int u = u0 + G;
+          const bool cur = u < 64;
+          const int uu = cur ? u : u - 64;
+          const int32_t dx = __builtin_amdgcn_readlane(cur ? cd.x : nd.x, uu);
+          const int32_t dy = __builtin_amdgcn_readlane(cur ? cd.y : nd.y, uu);
+          const int32_t dz = __builtin_amdgcn_readlane(cur ? cd.z : nd.z, uu);
+          const int32_t dw = __builtin_amdgcn_readlane(cur ? cd.w : nd.w, uu);
+          const int32_t kg = (int32_t)((uint32_t)dy >> 24);
+          kmax = kg > kmax ? kg : kmax;
+          const bool mine = s == G;
+          ao = mine ? make64(dx, dy & 0xffffff) : ao;
+          bo = mine ? make64(dz, dw) : bo;
+          k = mine ? kg : k;
+        }
+      });
+      frem -= cnt;
+      qi += cnt;
+      if (qi - qb >= 64) {
+        qb += 64;
+        cd = nd;
+        settle(cd);
+        load_desc(qb + 64, nd);
+      }
+    }
+    sw[d] = fm | (fn << 5) | (kmax << 10) | ((int32_t)fok << 15) | ((int32_t)(frem == 0) << 16);
+    sk[d] = k;
+    const int32_t mk = fm * k, kn = k * fn;  // before the cursor moves to the next C block
+    if (fok && frem == 0) next_entry();
+    // QA + QB loads per lane from the group's block starts, always issued;
+    // lanes past the block are masked off and keep stale values
+    const double* pa = P.Av + ao + li;
+    const double* pb = P.Bv + bo + li;
+#pragma unroll
+    for (int j = 0; j < QA; ++j)
+      if (li + 16 * j < mk) sa[d][j] = pa[16 * j];
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+      if (li + 16 * j < kn) sb[d][j] = pb[16 * j];
+  };
+
+  // the step in the stage: its packed word and the lane's group's inner size
+  int32_t stw = 0, stk = 0;
+  double* const As = wl + s * kGroup;
+  double* const Bs = As + kGroup / 2;
+  auto stage_write = [&](auto slot) {
+    constexpr int d = decltype(slot)::value;
+    stw = sw[d];
+    stk = sk[d];
+    const int32_t n = (stw >> 5) & 31;
+    // A as stored; B as stored with zeros past the block, so inner indices
+    // past the group's k (up to the step's largest) add nothing
+    const int32_t kn = stk * n;
+#pragma unroll
+    for (int j = 0; j < QA; ++j) As[li + 16 * j] = sa[d][j];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) Bs[li + 16 * j] = li + 16 * j < kn ? sb[d][j] : 0.0;
+  };
+
+  double acc[V];
+#pragma unroll
+  for (int x = 0; x < V; ++x) acc[x] = 0.0;
+  // Lane (g, rho, gam): A(2rho + i, t) = As[(2rho + i)*k + t], B(t, 2gam + j) = Bs[t*n + 2gam + j]
+  auto compute = [&]() {
+    const int32_t n = (stw >> 5) & 31, kmax = (stw >> 10) & 31;
+    const double* Ar = As + 2 * rho * stk;
+    const double* Bc = Bs + 2 * gam;
+#pragma unroll 4
+    for (int32_t t = 0; t < kmax; ++t) {
+      const double a0 = Ar[t], a1 = Ar[stk + t];
+      const double b0 = Bc[t * n], b1 = Bc[t * n + 1];
+      acc[0] = fma(a0, b0, acc[0]);
+      acc[1] = fma(a0, b1, acc[1]);
+      acc[2] = fma(a1, b0, acc[2]);
+      acc[3] = fma(a1, b1, acc[3]);
+    }
+  };
+
+  // Finish the C block of the step just multiplied: sum the groups, park
+  // alpha*acc row-major in the stage (free once multiplied), add beta*C_in
+  // and store coalesced.
+  auto finish = [&]() {
+    double* const tile = wl;
+#pragma unroll
+    for (int x = 0; x < V / 2; ++x) {
+      swap32(acc[x], acc[x + V / 2]);
+      acc[x] = acc[x] + acc[x + V / 2];
+    }
+#pragma unroll
+    for (int x = 0; x < V / 4; ++x) {
+      swap16(acc[x], acc[x + V / 4]);
+      acc[x] = acc[x] + acc[x + V / 4];
+    }
+    const int r = fr & 63;
+    ++fr;
+    const int32_t mn = __builtin_amdgcn_readlane(fifo_mn, r);
+    const int32_t m = mn & 255, n = mn >> 8;
+    const int64_t coff = make64(__builtin_amdgcn_readlane(fifo_co0, r), __builtin_amdgcn_readlane(fifo_co1, r));
+    const int64_t oo = make64(__builtin_amdgcn_readlane(fifo_oo0, r), __builtin_amdgcn_readlane(fifo_oo1, r));
+    wave_sync();  // every group has read the stage
+    // this lane's output is tile slot y = s (one of its group's 2x2)
+    {
+      const int y = s;
+      const int R = rho * RM + y / RN, Cc = gam * RN + y % RN;
+      if (R < m && Cc < n) tile[R * n + Cc] = P.alpha * acc[0];
+    }
+    wave_sync();
+    const int32_t mnv = m * n;
+    double* out = P.Cv + coff;
+    if (oo >= 0) {
+      const double* ov = P.Ov + oo;
+      const int e = lane < mnv ? lane : 0;
+      const double ol = ov[e];
+      if (lane < mnv) out[lane] = tile[lane] + P.beta * ol;
+    } else {
+      if (lane < mnv) out[lane] = tile[lane];
+    }
+#pragma unroll
+    for (int x = 0; x < V; ++x) acc[x] = 0.0;
+  };
+  static_assert(MP * NP == 64, "one output per lane after the group sum");
+
+  // Prime: slots 0..D-1.  Step i (slot i mod D): write the slot into the
+  // stage, refill it with step i+D, multiply; finish the C block if the step
+  // ends it.
+  static_for<0, D>([&](auto d) { fetch(d); });
+  bool more = true;
+  while (more) {
+    static_for<0, D>([&](auto idx) {
+      if (!more) return;
+      if (!((sw[decltype(idx)::value] >> 15) & 1)) {
+        more = false;
+        return;
+      }
+      wave_sync();
+      stage_write(idx);
+      fetch(idx);
+      wave_sync();
+      compute();
+      if ((stw >> 16) & 1) finish();
+    });
+  }
+}
+
 // One persistent launch over every class: each wave runs its share of the
 // classes selected by `mask` (bit c = class c) in turn.  D0, D1, D2 are the
 // products in flight of the 8x8, 8x16 and 16x8 classes (16x16 always holds 2:
-// four 16x16 slots do not fit beside its accumulators).
+// four 16x16 slots do not fit beside its accumulators); D0 = 1 selects the
+// four-products-per-step form of the 8x8 class.
 template <int D0, int D1, int D2>
 __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
@@ -586,7 +852,12 @@ __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restri
   int32_t b[5];
 #pragma unroll
   for (int x = 0; x < 5; ++x) b[x] = cls_start[x];
-  if (mask & 1) small_class<8, 8, D0>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+  if (mask & 1) {
+    if constexpr (D0 == 1)
+      small_quad<1>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+    else
+      small_class<8, 8, D0>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+  }
   if (mask & 2) small_class<8, 16, D1>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
   if (mask & 4) small_class<16, 8, D2>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
   if (mask & 8) small_class<16, 16, 2>(P, wl, b[3], b[4], xcd, wpx, wix, lane);
@@ -641,10 +912,10 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
 // Compiled pipeline variants, indexed by the tuner's variant number.
 using SmallKernel = void (*)(const double*, const double*, const double*, const int4*, const int32_t*,
                             const int64_t*, const int4*, double*, double, double, int32_t);
-constexpr SmallKernel kSmallKernels[] = {k_numeric_small<2, 2, 2>, k_numeric_small<4, 2, 2>, k_numeric_small<6, 2, 2>,
-                                         k_numeric_small<4, 4, 2>, k_numeric_small<4, 2, 4>, k_numeric_small<4, 4, 4>};
+constexpr SmallKernel kSmallKernels[] = {k_numeric_small<1, 2, 2>, k_numeric_small<4, 2, 2>, k_numeric_small<1, 4, 2>,
+                                         k_numeric_small<1, 2, 4>, k_numeric_small<1, 4, 4>, k_numeric_small<2, 2, 2>};
 
-constexpr int kSmallDepths[][4] = {{2, 2, 2, 2}, {4, 2, 2, 2}, {6, 2, 2, 2}, {4, 4, 2, 2}, {4, 2, 4, 2}, {4, 4, 4, 2}};
+constexpr int kSmallDepths[][4] = {{1, 2, 2, 2}, {4, 2, 2, 2}, {1, 4, 2, 2}, {1, 2, 4, 2}, {1, 4, 4, 2}, {2, 2, 2, 2}};
 static_assert(sizeof(kSmallKernels) / sizeof(kSmallKernels[0]) == kSmallVariants, "variant table");
 static_assert(sizeof(kSmallDepths) / sizeof(kSmallDepths[0]) == kSmallVariants, "variant table");
 

@@ -17,9 +17,10 @@ The table is saved as JSON, one entry per edge set:
 tune_gfx950.json next to this file, if present, when the library is first
 used.
 
-    python -m paper_1708_03604_amd.tune [--nmol 3000] [--reps 5]
+    python -m paper_1708_03604_amd.tune [--nmol 3000] [--se-nmol 40000] [--reps 5]
 
-tunes the atom-blocked water product (O: 13, H: 5) and writes the table.
+tunes the atom-blocked water product (O: 13, H: 5) and a semi-empirical-shaped
+product (6x6 blocks) and writes the table.
 """
 import argparse
 import json
@@ -78,21 +79,26 @@ def main():
     from . import workloads as W
     ap = argparse.ArgumentParser()
     ap.add_argument("--nmol", type=int, default=3000)
+    ap.add_argument("--se-nmol", type=int, default=40000)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=TABLE)
     args = ap.parse_args()
-    w = W.water_atoms(nmol=args.nmol)
-    st = torch.cuda.Stream()
-    dA = bsmm.Matrix.from_csr(w.A, st)
-    dB = bsmm.Matrix.from_csr(w.B, st)
-    dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, st)
-    entry = tune(w.alpha, dA, dB, w.beta, None, dC, w.eps, args.reps, st)
-    if entry is None:
-        raise SystemExit("the small-block path does not serve this product")
-    print(json.dumps(entry), flush=True)
-    save([entry], args.out, note=f"tuned on {w.name}, {args.reps} launches per variant and class; ms per launch")
-    for m in (dA, dB, dC):
-        m.close()
+    entries, names = [], []
+    for w in (W.water_atoms(nmol=args.nmol), W.semi_empirical(nmol=args.se_nmol)):
+        st = torch.cuda.Stream()
+        dA = bsmm.Matrix.from_csr(w.A, st)
+        dB = bsmm.Matrix.from_csr(w.B, st)
+        dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, st)
+        entry = tune(w.alpha, dA, dB, w.beta, None, dC, w.eps, args.reps, st)
+        if entry is None:
+            raise SystemExit(f"the small-block path does not serve {w.name}")
+        print(w.name, json.dumps(entry), flush=True)
+        entries.append(entry)
+        names.append(w.name)
+        for m in (dA, dB, dC):
+            m.close()
+    save(entries, args.out, note=f"tuned on {', '.join(names)}; {args.reps} launches per variant and class; "
+                                 "ms per launch")
 
 
 if __name__ == "__main__":
