@@ -22,12 +22,16 @@ static_assert((1 << kHashBits) == kHashSlots, "hash size");
 static_assert(kMaxRowA % kSymThreads == 0, "A chunking");
 static_assert(kMaxRowBlocks % kSymThreads == 0, "row chunking");
 
-__device__ __forceinline__ uint32_t hash_of(int32_t j) { return ((uint32_t)j * 2654435761u) >> (32 - kHashBits); }
+template <int HB>
+__device__ __forceinline__ uint32_t hash_of(int32_t j) { return ((uint32_t)j * 2654435761u) >> (32 - HB); }
 
-// Insert block column j; returns its slot (or -1 if the table is full).
+// Insert block column j into a table of 2^HB slots; returns its slot (or -1
+// if the table is full).
+template <int HB>
 __device__ __forceinline__ int hash_insert(int32_t* hkey, int32_t j, bool* fresh) {
-  uint32_t h = hash_of(j);
-  for (int probe = 0; probe < kHashSlots; ++probe) {
+  constexpr int kSlots = 1 << HB;
+  uint32_t h = hash_of<HB>(j);
+  for (int probe = 0; probe < kSlots; ++probe) {
     const int32_t prev = atomicCAS(&hkey[h], -1, j);
     if (prev == -1) {
       *fresh = true;
@@ -37,19 +41,21 @@ __device__ __forceinline__ int hash_insert(int32_t* hkey, int32_t j, bool* fresh
       *fresh = false;
       return (int)h;
     }
-    h = (h + 1) & (kHashSlots - 1);
+    h = (h + 1) & (kSlots - 1);
   }
   *fresh = false;
   return -1;
 }
 
+template <int HB>
 __device__ __forceinline__ int hash_find(const int32_t* hkey, int32_t j) {
-  uint32_t h = hash_of(j);
-  for (int probe = 0; probe < kHashSlots; ++probe) {
+  constexpr int kSlots = 1 << HB;
+  uint32_t h = hash_of<HB>(j);
+  for (int probe = 0; probe < kSlots; ++probe) {
     const int32_t k = hkey[h];
     if (k == j) return (int)h;
     if (k == -1) return -1;
-    h = (h + 1) & (kHashSlots - 1);
+    h = (h + 1) & (kSlots - 1);
   }
   return -1;
 }
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
         const int32_t j = jj[u];
         nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[pp[u]];
         bool fresh;
-        const int h = hash_insert(hkey, j, &fresh);
+        const int h = hash_insert<kHashBits>(hkey, j, &fresh);
         if (h < 0) {
           s_bad = 1;
         } else if (fresh) {
@@ -219,7 +225,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
       for (int32_t q = g.Cin.row_ptr[i] + tid; q < o1; q += kSymThreads) {
         const int32_t j = g.Cin.col_idx[q];
         bool fresh;
-        const int h = hash_insert(hkey, j, &fresh);
+        const int h = hash_insert<kHashBits>(hkey, j, &fresh);
         if (h < 0) {
           s_bad = 1;
         } else if (fresh) {
@@ -249,25 +255,39 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
 // ------------------------------------------------------------------ fill
 
 // Row state of the fill pass (the count pass also needs the inner sizes).
+template <int RA>
 struct RowFill {
-  int32_t qs[kMaxRowA];        // first B block of B row k_p
-  int32_t pre[kMaxRowA + 1];   // exclusive prefix of B row lengths
-  double nrm[kMaxRowA];        // norm of A(i, k_p)
+  int32_t qs[RA];        // first B block of B row k_p
+  int32_t pre[RA + 1];   // exclusive prefix of B row lengths
+  double nrm[RA];        // norm of A(i, k_p)
 };
 
-// The row's candidates, in chunks of kCandCache, hold the hash slot of their
-// block column (or -1 when the filter drops them).
-constexpr int kCandCache = 8192;
-static_assert(kHashSlots <= 32767, "slots must fit in int16");
+// Capacities of one form of the fill pass: 2^HB hash slots, at most RA
+// stored A blocks and RB result blocks per row, and the row's candidates
+// cached in chunks of CC (each holds the hash slot of its block column, or -1
+// when the filter drops it).  The fill runs in two forms: a small one (34 KB
+// of LDS, four workgroups per CU) for the rows that fit it, and a large one
+// (78 KB, two per CU) for the rest; rows do not interact, so each form takes
+// its own rows.
+template <int HB, int RA, int RB, int CC>
+struct FillCaps {
+  static constexpr int kBits = HB, kSlots = 1 << HB, kRowA = RA, kRowC = RB, kCand = CC;
+  static_assert(kSlots <= 32767, "slots must fit in int16");
+  static_assert(RA % kSymThreads == 0 && RB % kSymThreads == 0, "row chunking");
+  static_assert(2 * RB <= kSlots, "hash load at most one half");
+};
+using FillSmall = FillCaps<10, 256, 512, 4096>;
+using FillLarge = FillCaps<kHashBits, kMaxRowA, kMaxRowBlocks, 8192>;
 
-__device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill& ra, int32_t* a0_out, int32_t* na_out) {
+template <int RA>
+__device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, int32_t* a0_out, int32_t* na_out) {
   const int tid = threadIdx.x;
   const int32_t a0 = g.A.row_ptr[i];
   const int32_t nA = g.A.row_ptr[i + 1] - a0;
   *a0_out = a0;
   *na_out = nA;
-  if (nA > kMaxRowA) return -1;
-  constexpr int kPer = kMaxRowA / kSymThreads;
+  if (nA > RA) return -1;
+  constexpr int kPer = RA / kSymThreads;
   int32_t len[kPer];
   int64_t mysum = 0;
 #pragma unroll
@@ -297,7 +317,8 @@ __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill& ra, int32
   return (int32_t)total;
 }
 
-__device__ __forceinline__ int32_t fill_entry_of(const RowFill& ra, int32_t nA, int32_t t) {
+template <int RA>
+__device__ __forceinline__ int32_t fill_entry_of(const RowFill<RA>& ra, int32_t nA, int32_t t) {
   int lo = 0, hi = nA - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -307,44 +328,64 @@ __device__ __forceinline__ int32_t fill_entry_of(const RowFill& ra, int32_t nA, 
   return lo;
 }
 
-__device__ __forceinline__ bool fill_keep(const SymArgs& g, const RowFill& ra, int32_t p, int32_t q) {
+template <int RA>
+__device__ __forceinline__ bool fill_keep(const SymArgs& g, const RowFill<RA>& ra, int32_t p, int32_t q) {
   if (!g.use_eps) return true;
   const double prod = ra.nrm[p] * g.normB[q];
   return prod > g.eps;
 }
 
-// One workgroup per C block row.  After the hash has merged the kept
+// LDS of one workgroup of the fill pass.
+template <class Cap>
+struct FillShared {
+  int32_t hkey[Cap::kSlots];
+  int32_t hcnt[Cap::kSlots];  // product count per slot, then the slot's rank
+  int32_t hold[Cap::kSlots];
+  RowFill<Cap::kRowA> ra;
+  int32_t ekey[Cap::kRowC];
+  int32_t eslot[Cap::kRowC];
+  int32_t spre[Cap::kRowC];
+  int32_t cursor[Cap::kRowC];
+  int32_t svs[Cap::kRowC];
+  int16_t cslot[Cap::kCand];
+  int32_t s_ne;
+};
+
+// Fill C block row i (one workgroup).  After the hash has merged the kept
 // candidates by column, the columns are ranked (sorted pattern), the counts
 // scanned (each C block's slice of the stack), and the products placed in
 // ascending A entry order, i.e. ascending k (the candidates of one A entry
 // have distinct columns, so within a C block the entries order its products).
-__global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
-  __shared__ int32_t hkey[kHashSlots];
-  __shared__ int32_t hcnt[kHashSlots];  // product count per slot, then the slot's rank
-  __shared__ int32_t hold[kHashSlots];
-  __shared__ RowFill ra;
-  __shared__ int32_t ekey[kMaxRowBlocks];
-  __shared__ int32_t eslot[kMaxRowBlocks];
-  __shared__ int32_t spre[kMaxRowBlocks];
-  __shared__ int32_t cursor[kMaxRowBlocks];
-  __shared__ int32_t svs[kMaxRowBlocks];
-  __shared__ int16_t cslot[kCandCache];
-  __shared__ int32_t s_ne;
+template <class Cap>
+__device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
+  int32_t* const hkey = sh.hkey;
+  int32_t* const hcnt = sh.hcnt;
+  int32_t* const hold = sh.hold;
+  RowFill<Cap::kRowA>& ra = sh.ra;
+  int32_t* const ekey = sh.ekey;
+  int32_t* const eslot = sh.eslot;
+  int32_t* const spre = sh.spre;
+  int32_t* const cursor = sh.cursor;
+  int32_t* const svs = sh.svs;
+  int16_t* const cslot = sh.cslot;
+  constexpr int kHashBitsF = Cap::kBits;
+  constexpr int kHashSlotsF = Cap::kSlots;
+  constexpr int kMaxRowBlocksF = Cap::kRowC;
+  constexpr int kCandCacheF = Cap::kCand;
   const int tid = threadIdx.x;
-  constexpr int kPer = kMaxRowBlocks / kSymThreads;
-  if (g.totals[kTotAbort]) return;
-  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
-    for (int h = tid; h < kHashSlots; h += kSymThreads) {
+  constexpr int kPer = kMaxRowBlocksF / kSymThreads;
+  {
+    for (int h = tid; h < kHashSlotsF; h += kSymThreads) {
       hkey[h] = -1;
       hcnt[h] = 0;
       hold[h] = -1;
     }
-    if (tid == 0) s_ne = 0;
+    if (tid == 0) sh.s_ne = 0;
     __syncthreads();
     int32_t a0, nA;
     const int32_t T = load_row_fill(g, i, ra, &a0, &nA);
-    if (T < 0) continue;  // uniform over the workgroup; reported by the count pass
-    const bool one_chunk = T <= kCandCache;
+    if (T < 0) return;  // uniform over the workgroup; reported by the count pass
+    const bool one_chunk = T <= kCandCacheF;
     for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
       int32_t jj[kCandBatch];
       bool kk[kCandBatch];
@@ -362,7 +403,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
         int h = -1;
         if (kk[u]) {
           bool fresh;
-          h = hash_insert(hkey, jj[u], &fresh);
+          h = hash_insert<kHashBitsF>(hkey, jj[u], &fresh);
           if (h >= 0) atomicAdd(&hcnt[h], 1);
         }
         if (one_chunk && t < T) cslot[t] = (int16_t)h;
@@ -372,23 +413,23 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
       const int32_t o1 = g.Cin.row_ptr[i + 1];
       for (int32_t q = g.Cin.row_ptr[i] + tid; q < o1; q += kSymThreads) {
         bool fresh;
-        const int h = hash_insert(hkey, g.Cin.col_idx[q], &fresh);
+        const int h = hash_insert<kHashBitsF>(hkey, g.Cin.col_idx[q], &fresh);
         if (h >= 0) hold[h] = q;
       }
     }
     __syncthreads();
-    for (int h = tid; h < kHashSlots; h += kSymThreads) {
+    for (int h = tid; h < kHashSlotsF; h += kSymThreads) {
       if (hkey[h] >= 0) {
-        const int e = atomicAdd(&s_ne, 1);
-        if (e < kMaxRowBlocks) {
+        const int e = atomicAdd(&sh.s_ne, 1);
+        if (e < kMaxRowBlocksF) {
           ekey[e] = hkey[h];
           eslot[e] = h;
         }
       }
     }
     __syncthreads();
-    const int32_t nC = s_ne;
-    if (nC > kMaxRowBlocks) continue;  // reported by the count pass
+    const int32_t nC = sh.s_ne;
+    if (nC > kMaxRowBlocksF) return;  // reported by the count pass
     // Rank the distinct columns (rank = number of smaller columns), move the
     // counts into rank order and leave each slot's rank in hcnt.
     const int32_t crow = g.c_row_ptr[i];
@@ -441,8 +482,8 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
     for (int r = tid; r < nC; r += kSymThreads) rmask[r] = 0;
     __syncthreads();
     const int64_t prow = g.row_pstart[i];
-    for (int32_t t0 = 0; t0 < T; t0 += kCandCache) {
-      const int32_t t1 = T - t0 > kCandCache ? t0 + kCandCache : T;
+    for (int32_t t0 = 0; t0 < T; t0 += kCandCacheF) {
+      const int32_t t1 = T - t0 > kCandCacheF ? t0 + kCandCacheF : T;
       if (!one_chunk) {
         for (int32_t tb = t0 + tid; tb < t1; tb += kCandBatch * kSymThreads) {
           int32_t jj[kCandBatch];
@@ -458,7 +499,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
 #pragma unroll
           for (int u = 0; u < kCandBatch; ++u) {
             const int32_t t = tb + u * kSymThreads;
-            if (t < t1) cslot[t - t0] = (int16_t)(kk[u] ? hash_find(hkey, jj[u]) : -1);
+            if (t < t1) cslot[t - t0] = (int16_t)(kk[u] ? hash_find<kHashBitsF>(hkey, jj[u]) : -1);
           }
         }
         __syncthreads();
@@ -504,6 +545,44 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill(SymArgs g) {
   }
 }
 
+__device__ __forceinline__ bool fill_fits_small(const SymArgs& g, int32_t i) {
+  return g.A.row_ptr[i + 1] - g.A.row_ptr[i] <= FillSmall::kRowA &&
+         g.c_row_ptr[i + 1] - g.c_row_ptr[i] <= FillSmall::kRowC;
+}
+
+// Small form: every row that fits its capacities, one workgroup per row.
+__global__ __launch_bounds__(kSymThreads) void k_sym_fill_small(SymArgs g) {
+  __shared__ FillShared<FillSmall> sh;
+  if (g.totals[kTotAbort]) return;
+  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+    if (!fill_fits_small(g, i)) continue;  // uniform: every thread reads the same sizes
+    fill_row<FillSmall>(g, i, sh);
+    __syncthreads();
+  }
+}
+
+// Large form: the remaining rows.  Each workgroup looks at 256 rows at a time,
+// one per thread, lists the ones the small form leaves and fills them in turn.
+__global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
+  __shared__ FillShared<FillLarge> sh;
+  __shared__ int32_t rows[kSymThreads];
+  __shared__ int32_t nrows;
+  if (g.totals[kTotAbort]) return;
+  const int tid = threadIdx.x;
+  for (int32_t base = blockIdx.x * kSymThreads; base < g.A.nbrows; base += gridDim.x * kSymThreads) {
+    if (tid == 0) nrows = 0;
+    __syncthreads();
+    const int32_t i = base + tid;
+    if (i < g.A.nbrows && !fill_fits_small(g, i)) rows[atomicAdd(&nrows, 1)] = i;
+    __syncthreads();
+    const int32_t n = nrows;
+    for (int32_t x = 0; x < n; ++x) {
+      fill_row<FillLarge>(g, rows[x], sh);
+      __syncthreads();
+    }
+  }
+}
+
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
@@ -514,7 +593,11 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
 hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
-  hipLaunchKernelGGL(k_sym_fill, dim3(grid), dim3(kSymThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sym_fill_small, dim3(grid), dim3(kSymThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int batches = (a.A.nbrows + kSymThreads - 1) / kSymThreads;
+  hipLaunchKernelGGL(k_sym_fill_large, dim3(batches < 512 ? batches : 512), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -318,3 +318,40 @@ def test_water_atoms_sampled_rows():
     got = gpu_multiply(w.A, w.B, None, w.alpha, w.beta, w.eps)
     rows = sorted(set(np.random.default_rng(7).choice(w.A.nbrows, 24, replace=False).tolist()) | {0, 8999})
     sampled_rows_check(w, rows, got)
+
+
+def _rows_dense_mask(seed, nr, nc, dense_rows, p):
+    rng = np.random.default_rng(seed)
+    mask = rng.random((nr, nc)) < p
+    mask[dense_rows, :] = True
+    return mask
+
+
+@pytest.mark.parametrize("case", ["long_a_rows", "wide_c_rows"])
+def test_fill_both_forms(case):
+    # Rows beyond the small fill form (more than 256 A blocks, or more than
+    # 512 result blocks) run in the large form; the others in the small one,
+    # in the same multiply.
+    if case == "long_a_rows":
+        nr, nk, nc = 24, 600, 40
+        ma = _rows_dense_mask(501, nr, nk, [0, 7, 23], 0.05)
+        mb = _rows_dense_mask(502, nk, nc, [], 0.3)
+    else:
+        nr, nk, nc = 24, 30, 900
+        ma = _rows_dense_mask(503, nr, nk, [], 0.2)
+        mb = _rows_dense_mask(504, nk, nc, [3, 11], 0.02)
+    rs = np.resize(np.array([1, 2, 3], dtype=np.int32), nr)
+    ks = np.resize(np.array([2, 1], dtype=np.int32), nk)
+    cs = np.resize(np.array([1, 3, 2], dtype=np.int32), nc)
+    rpa, cia = W.pattern_from_mask(ma)
+    rpb, cib = W.pattern_from_mask(mb)
+    A = W.with_pattern(rs, ks, rpa, cia)
+    A.values = W.values_int(505, A.nvals)
+    B = W.with_pattern(ks, cs, rpb, cib)
+    B.values = W.values_int(506, B.nvals)
+    ref = oracle.multiply(1.0, A, B, 0.0, None, 0.0)
+    nA = np.diff(A.row_ptr)
+    nC = np.diff(ref.row_ptr)
+    assert (nA > 256).any() or (nC > 512).any()
+    assert ((nA <= 256) & (nC <= 512)).any()
+    check(ref, gpu_multiply(A, B, None, 1.0, 0.0, 0.0), exact=True)
