@@ -195,6 +195,9 @@ hipEvent_t* mark(bsmm_matrix* m, size_t base, int k, hipStream_t s) {
 // Upper bound on the stored blocks / values (exact unless device-sized).
 int64_t blocks_bound(const bsmm_matrix* m) { return m->cap_nnzb > 0 ? m->cap_nnzb : m->nnzb; }
 
+// Values of the largest possible block of m.
+int64_t max_block(const bsmm_matrix* m) { return (int64_t)m->max_edge * m->max_edge; }
+
 // Bring the host copy of a device-sized matrix's sizes (and of the counters of
 // its last multiply) up to date; synchronises `s`.  A reserved operation that
 // overflowed leaves the matrix empty and is reported here.
@@ -400,7 +403,7 @@ bsmm_status bsmm_norms(bsmm_mat m, double* out, void* stream) {
   g_err.clear();
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
   if (!out && blocks_bound(m) > 0) return fail(BSMM_E_ARG, "NULL output");
-  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, blocks_bound(m), out,
+  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, blocks_bound(m), max_block(m), out,
                              reinterpret_cast<hipStream_t>(stream)));
   return BSMM_OK;
 }
@@ -562,14 +565,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     const int64_t ba = blocks_bound(A), bb = blocks_bound(B);
     if (C->norm_a.ensure(std::max<int64_t>(ba, 1)) != hipSuccess)
       return fail(BSMM_E_NOMEM, "scratch allocation failed");
-    HIP_TRY(launch_block_norms(A->cur.blk_off.p, A->cur.values.p, A->dsz.p, ba, C->norm_a.p, s));
+    HIP_TRY(launch_block_norms(A->cur.blk_off.p, A->cur.values.p, A->dsz.p, ba, max_block(A), C->norm_a.p, s));
     normA = C->norm_a.p;
     if (B == A) {
       normB = normA;
     } else {
       if (C->norm_b.ensure(std::max<int64_t>(bb, 1)) != hipSuccess)
         return fail(BSMM_E_NOMEM, "scratch allocation failed");
-      HIP_TRY(launch_block_norms(B->cur.blk_off.p, B->cur.values.p, B->dsz.p, bb, C->norm_b.p, s));
+      HIP_TRY(launch_block_norms(B->cur.blk_off.p, B->cur.values.p, B->dsz.p, bb, max_block(B), C->norm_b.p, s));
       normB = C->norm_b.p;
     }
   }
@@ -754,7 +757,7 @@ bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream) {
       m->scan_tmp.ensure(std::max(scan_tmp_elems(bound), scan_tmp_elems(m->nbrows)) + 2) != hipSuccess ||
       ensure_storage(m->spare, m->nbrows, bound, vbound) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
-  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, bound, m->norm_self.p, s));
+  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, bound, max_block(m), m->norm_self.p, s));
   HIP_TRY(launch_filter(m->cur.row_ptr.p, m->cur.col_idx.p, m->cur.blk_off.p, m->cur.values.p, m->nbrows, m->dsz.p,
                         bound, m->norm_self.p, eps, m->fkeep.p, m->fvsz.p, m->fpos.p, m->fvoff.p, m->scan_tmp.p,
                         m->spare.row_ptr.p, m->spare.col_idx.p, m->spare.blk_off.p, m->spare.values.p, s));

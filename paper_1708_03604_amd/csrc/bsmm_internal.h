@@ -103,9 +103,10 @@ struct NumArgs {
 };
 
 // Launchers (all enqueue on `s`; they return the launch status).
-// Norms of the first *d_nnzb blocks; bound >= *d_nnzb sizes the launch.
+// Norms of the first *d_nnzb blocks; bound >= *d_nnzb sizes the launch;
+// max_block bounds the values of one block (selects the launch shape).
 hipError_t launch_block_norms(const int64_t* blk_off, const double* values, const int64_t* d_nnzb, int64_t bound,
-                              double* out, hipStream_t s);
+                              int64_t max_block, double* out, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Zero the value slack after the result and write its size record
 // dsz = {nnzb, nvals, error bits}.

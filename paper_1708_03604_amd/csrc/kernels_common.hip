@@ -32,9 +32,55 @@ __global__ __launch_bounds__(256) void k_block_norms(const int64_t* __restrict__
   }
 }
 
+// Blocks of at most kNormSmall values: four blocks per wave, 16 lanes each.
+// Lane j of a group keeps the partials j, j+16, j+32 and j+48 of the 64-lane
+// order above (element e feeds partial e mod 64, ascending e), and the tree
+// adds them in the same order: partials l and l+32 within the lane, then l
+// and l+16 within the lane, then across lanes for 8, 4, 2, 1.  Results are
+// bit-identical to k_block_norms.
+constexpr int kNormSmall = 256;
+
+__global__ __launch_bounds__(256) void k_block_norms_small(const int64_t* __restrict__ blk_off,
+                                                           const double* __restrict__ values,
+                                                           const int64_t* __restrict__ d_nnzb,
+                                                           double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4, j = lane & 15;
+  const int32_t nnzb = (int32_t)*d_nnzb;
+  const int32_t nwaves = gridDim.x * (blockDim.x >> 6);
+  for (int32_t b0 = 4 * (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); b0 < nnzb; b0 += 4 * nwaves) {
+    const int32_t b = b0 + grp;
+    const bool ok = b < nnzb;
+    const int64_t o = ok ? blk_off[b] : 0;
+    const int64_t n = ok ? blk_off[b + 1] - o : 0;
+    const double* x = values + o;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    for (int64_t e = j; e < n; e += 64) {
+      q0 = fma(x[e], x[e], q0);
+      if (e + 16 < n) q1 = fma(x[e + 16], x[e + 16], q1);
+      if (e + 32 < n) q2 = fma(x[e + 32], x[e + 32], q2);
+      if (e + 48 < n) q3 = fma(x[e + 48], x[e + 48], q3);
+    }
+    q0 = q0 + q2;
+    q1 = q1 + q3;
+    q0 = q0 + q1;
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) {
+      const double other = __shfl_down(q0, d, 16);
+      if (j < d) q0 = q0 + other;
+    }
+    if (ok && j == 0) out[b] = sqrt(q0);
+  }
+}
+
 hipError_t launch_block_norms(const int64_t* blk_off, const double* values, const int64_t* d_nnzb, int64_t bound,
-                              double* out, hipStream_t s) {
+                              int64_t max_block, double* out, hipStream_t s) {
   if (bound <= 0) return hipSuccess;
+  if (max_block <= kNormSmall) {
+    int64_t blocks = (bound + 15) / 16;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_block_norms_small, dim3((uint32_t)blocks), dim3(256), 0, s, blk_off, values, d_nnzb, out);
+    return hipGetLastError();
+  }
   int64_t blocks = (bound + 3) / 4;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_block_norms, dim3((uint32_t)blocks), dim3(256), 0, s, blk_off, values, d_nnzb, out);

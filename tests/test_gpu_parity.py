@@ -118,9 +118,10 @@ def test_square_same_operand_and_in_place():
     check(ref, gpu_multiply(X, X, Co, -1.0, 1.0, 5.0, in_place=True))
 
 
-def test_norms_bit_exact():
+@pytest.mark.parametrize("sizes", [[1, 2, 5, 13, 23, 30, 64, 65, 100],   # one block per wave
+                                   [1, 2, 3, 5, 6, 8, 13, 15, 16] * 3])  # blocks of <= 256 values: four per wave
+def test_norms_bit_exact(sizes):
     import torch
-    sizes = [1, 2, 5, 13, 23, 30, 64, 65, 100]
     M = W.random_matrix(41, sizes, sizes[::-1], 0.7)
     M.values[:64] *= 1e-160       # tiny and huge magnitudes
     M.values[-64:] *= 1e150
