@@ -84,23 +84,25 @@ __device__ int64_t sym_scan(int64_t v, int64_t* total) {
 }
 
 // Row state in LDS common to both passes.
+template <int RA>
 struct RowA {
-  int32_t qs[kMaxRowA];        // first B block of B row k_p
-  int32_t ks[kMaxRowA];        // inner block size of k_p
-  int32_t pre[kMaxRowA + 1];   // exclusive prefix of B row lengths
-  double nrm[kMaxRowA];        // norm of A(i, k_p)
+  int32_t qs[RA];        // first B block of B row k_p
+  int32_t ks[RA];        // inner block size of k_p
+  int32_t pre[RA + 1];   // exclusive prefix of B row lengths
+  double nrm[RA];        // norm of A(i, k_p)
 };
 
 // Load the A entries of row i and the candidate prefix.  Returns the number of
 // candidates T (or -1 if the row is outside the supported limits).
-__device__ int32_t load_row(const SymArgs& g, int32_t i, RowA& ra, int32_t* a0_out, int32_t* na_out) {
+template <int RA>
+__device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* a0_out, int32_t* na_out) {
   const int tid = threadIdx.x;
   const int32_t a0 = g.A.row_ptr[i];
   const int32_t nA = g.A.row_ptr[i + 1] - a0;
   *a0_out = a0;
   *na_out = nA;
-  if (nA > kMaxRowA) return -1;
-  constexpr int kPer = kMaxRowA / kSymThreads;
+  if (nA > RA) return -1;
+  constexpr int kPer = RA / kSymThreads;
   int32_t len[kPer];
   int64_t mysum = 0;
 #pragma unroll
@@ -132,7 +134,8 @@ __device__ int32_t load_row(const SymArgs& g, int32_t i, RowA& ra, int32_t* a0_o
 }
 
 // Candidate t of the row -> (A entry p, B block q).
-__device__ __forceinline__ void candidate(const RowA& ra, int32_t nA, int32_t t, int32_t* p_out, int32_t* q_out) {
+template <int RA>
+__device__ __forceinline__ void candidate(const RowA<RA>& ra, int32_t nA, int32_t t, int32_t* p_out, int32_t* q_out) {
   int lo = 0, hi = nA - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -143,7 +146,8 @@ __device__ __forceinline__ void candidate(const RowA& ra, int32_t nA, int32_t t,
   *q_out = ra.qs[lo] + (t - ra.pre[lo]);
 }
 
-__device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA& ra, int32_t p, int32_t q) {
+template <int RA>
+__device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA<RA>& ra, int32_t p, int32_t q) {
   if (!g.use_eps) return true;
   const double prod = ra.nrm[p] * g.normB[q];
   return prod > g.eps;
@@ -156,16 +160,32 @@ __device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA& ra, i
 // flight per thread (rows of thousands of candidates are latency-bound).
 constexpr int kCandBatch = 4;
 
-__global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
-  __shared__ int32_t hkey[kHashSlots];
-  __shared__ RowA ra;
-  __shared__ int32_t s_nc;
-  __shared__ unsigned long long s_sumn;
-  __shared__ unsigned long long s_np;
-  __shared__ unsigned long long s_nf;
-  __shared__ int s_bad;
+// LDS of one workgroup of the count pass.  The hash always has the full size
+// (the row's distinct columns are what the pass counts); the A entries of
+// the row take RA slots.
+template <int RA>
+struct CountShared {
+  int32_t hkey[kHashSlots];
+  RowA<RA> ra;
+  int32_t s_nc;
+  unsigned long long s_sumn;
+  unsigned long long s_np;
+  unsigned long long s_nf;
+  int s_bad;
+};
+
+// Count C block row i (one workgroup).
+template <int RA>
+__device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
+  int32_t* const hkey = sh.hkey;
+  RowA<RA>& ra = sh.ra;
+  int32_t& s_nc = sh.s_nc;
+  unsigned long long& s_sumn = sh.s_sumn;
+  unsigned long long& s_np = sh.s_np;
+  unsigned long long& s_nf = sh.s_nf;
+  int& s_bad = sh.s_bad;
   const int tid = threadIdx.x;
-  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+  {
     for (int h = tid; h < kHashSlots; h += kSymThreads) hkey[h] = -1;
     if (tid == 0) {
       s_nc = 0;
@@ -187,7 +207,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
         g.row_nf[i] = 0;
       }
       __syncthreads();
-      continue;
+      return;
     }
     uint32_t np = 0;
     uint64_t nf = 0;
@@ -249,6 +269,35 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count(SymArgs g) {
       g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
     }
     __syncthreads();
+  }
+}
+
+constexpr int kCountSmallRowA = 256;
+
+// Small form (13 KB of LDS, eight workgroups per CU): rows of at most 256 A blocks.
+__global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
+  __shared__ CountShared<kCountSmallRowA> sh;
+  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+    if (g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA) continue;  // uniform
+    count_row<kCountSmallRowA>(g, i, sh);
+  }
+}
+
+// Large form: the longer rows (and rows beyond the limits, which it reports),
+// found 256 rows at a time as in the fill pass.
+__global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
+  __shared__ CountShared<kMaxRowA> sh;
+  __shared__ int32_t rows[kSymThreads];
+  __shared__ int32_t nrows;
+  const int tid = threadIdx.x;
+  for (int32_t base = blockIdx.x * kSymThreads; base < g.A.nbrows; base += gridDim.x * kSymThreads) {
+    if (tid == 0) nrows = 0;
+    __syncthreads();
+    const int32_t i = base + tid;
+    if (i < g.A.nbrows && g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA) rows[atomicAdd(&nrows, 1)] = i;
+    __syncthreads();
+    const int32_t n = nrows;
+    for (int32_t x = 0; x < n; ++x) count_row<kMaxRowA>(g, rows[x], sh);
   }
 }
 
@@ -586,7 +635,11 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
-  hipLaunchKernelGGL(k_sym_count, dim3(grid), dim3(kSymThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sym_count_small, dim3(grid), dim3(kSymThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int batches = (a.A.nbrows + kSymThreads - 1) / kSymThreads;
+  hipLaunchKernelGGL(k_sym_count_large, dim3(batches < 512 ? batches : 512), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 
