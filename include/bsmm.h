@@ -180,15 +180,15 @@ bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
  * products in flight per wave; a pipeline variant fixes that number per
  * class (bsmm_small_variant).  The tuning table maps a tuning key (the block
  * edges present in A's rows, A's columns and B's columns) to a variant;
- * multiplies whose key has no entry use variant 0.
+ * multiplies whose key has no entry use variant 1.
  *
  * bsmm_tune_small computes C_out = alpha*A*B + beta*C_in exactly as
  * bsmm_multiply with BSMM_FP64 does, then, if the small-block path served it,
  * times the products of each class alone with every variant (`reps` launches
  * each, HIP events on `stream`), enters the variant with the least total time
  * into the table and leaves C_out as that variant computes it (variants
- * with the same form of the 8x8 class give identical values; the two forms
- * add in different orders, both within FP64 rounding of the exact sum).
+ * with the same forms give identical values; the forms add in different
+ * orders, all within FP64 rounding of the exact sum).
  * Arguments as bsmm_multiply, plus:
  *   reps        : launches per variant and class, 1 ..  1000
  *   variant_out : chosen variant, or -1 when another path serves these sizes
@@ -203,9 +203,9 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
                             double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream);
 
 /* Products kept in flight per wave by variant v in the classes 8x8, 8x16,
- * 16x8 and 16x16 (rows x columns) into depths[4]; for the 8x8 class, 1 means
- * four products of one C block per step, one per 16-lane group.  BSMM_E_ARG
- * if v is out of range. */
+ * 16x8 and 16x16 (rows x columns) into depths[4]; 1 means several products
+ * of one C block per step (four for 8x8, one per 16-lane group; two for 8x16
+ * and 16x8, one per 32-lane group).  BSMM_E_ARG if v is out of range. */
 bsmm_status bsmm_small_variant(int32_t v, int32_t* depths);
 
 /* Tuning key of the product A*B: bits e-1, 16+e-1 and 32+e-1 are set for each

@@ -565,27 +565,33 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
   }
 }
 
-// Class 0 (C blocks of at most 8 x 8): four products of one C block per step,
-// one per group of 16 lanes.  Group g = lane >> 4 takes the step's g-th
-// product; its lanes own the same 2x2 outputs as in the K-slice layout of the
-// other classes (rows 2rho, 2rho+1, columns 2gam, 2gam+1), over every inner
-// index t < k, and the four groups' sums are added at the end of the C block
-// exactly as the K slices are.  A step holds the next one to four products of
-// the current C block (a C block's last step may leave groups without a
-// product: their k is 0 and their B block is all zeros).  Against one product
-// per step over four K slices this quarters the per-product instructions,
-// which bound the small-block kernel, at the cost of 4 FMA per 4 LDS reads.
+// Several products of one C block per step: PG products, one per group of
+// 64/PG lanes, each over 4/PG K slices (PG = 4 for the 8x8 class: one
+// product per 16 lanes over every inner index; PG = 2 for 8x16 and 16x8).
+// Lane l keeps the layout of the one-product form: quarter s = l >> 4 owns
+// K slice s mod (4/PG) of the product of group s / (4/PG), and rows and
+// columns by (rho, gam); the four quarters' sums are added at the end of the
+// C block exactly as the K slices are.  A step holds the next one to PG
+// products of the current C block (a C block's last step may leave groups
+// without a product: their k is 0 and their B block is all zeros).  Against
+// one product per step this divides the per-product instructions, which
+// bound the small-block kernel, by up to PG.
 //
-// One LDS stage (each group: A, then B, 128 doubles each; the tile of a
-// finished block is parked there too) and D register slots of four products.
-template <int D>
-__device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
-                                           int32_t xcd, int32_t wpx, int32_t wix, int lane) {
-  constexpr int MP = 8, NP = 8, RM = 2, RN = 2, V = 4;
-  constexpr int QA = 8, QB = 8;  // loads per lane of a group: A, B blocks of at most 128 elements
-  constexpr int kGroup = 256;    // LDS doubles per group: A (128), then B (128)
-  const int s = lane >> 4, rho = (lane >> 2) & 3, gam = lane & 3;  // s: the lane's group
-  const int li = lane & 15;
+// One LDS stage (each group: A then B; the tile of a finished block is
+// parked there too) and D register slots of PG products.
+template <int MP, int NP, int PG, int D>
+__device__ __forceinline__ void small_multi(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
+                                            int32_t xcd, int32_t wpx, int32_t wix, int lane) {
+  constexpr int RM = MP / 4, RN = NP / 4, V = RM * RN;
+  constexpr int GL = 64 / PG;                      // lanes per group
+  constexpr int KS = 4 / PG;                       // K slices per product
+  constexpr int kA = MP * 16, kB = 16 * NP;        // largest A and B blocks (k = 16)
+  constexpr int QA = kA / GL, QB = kB / GL;        // loads per lane of a group
+  constexpr int kGroup = kA + kB;                  // LDS doubles per group: A, then B
+  static_assert(PG * kGroup <= 2 * kStage, "one stage of PG groups fits the wave's LDS");
+  static_assert(kA % GL == 0 && kB % GL == 0 && V % 4 == 0, "tile shape");
+  const int s = lane >> 4, rho = (lane >> 2) & 3, gam = lane & 3;
+  const int grp = lane / GL, ks = s % KS, li = lane % GL;
 
   // This wave's run of the list: [E0, E1), products [Q0, Q0 + NQ) in list order.
   const int64_t L = L1 - L0;
@@ -663,7 +669,7 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
   // ---- slots: step X lives in slot X % D from its fetch to its stage write.
   // Packed word: m | n << 5 | kmax << 10 | valid << 15 | last << 16, where
   // kmax is the largest inner size of the step's products; sk holds the
-  // inner size of the lane's group (0: no product).
+  // inner size of the lane's group's product (0: none).
   double sa[D][QA], sb[D][QB];
   int32_t sw[D], sk[D];
   // masked-off lanes keep their previous values: start from zeros so that
@@ -680,11 +686,11 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
     int64_t ao = 0, bo = 0;
     int32_t k = 0, kmax = 0;
     if (fok && frem > 0) {
-      const int32_t cnt = frem < 4 ? frem : 4;
+      const int32_t cnt = frem < PG ? frem : PG;
       const int u0 = qi - qb;
       // descriptors u0 .. u0+cnt-1 of the current batch; past 63 they are
       // the first ones of the next batch
-      static_for<0, 4>([&](auto gi) {
+      static_for<0, PG>([&](auto gi) {
         constexpr int G = decltype(gi)::value;
         if (G < cnt) {
           const int u = u0 + G;
@@ -696,7 +702,7 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
           const int32_t dw = __builtin_amdgcn_readlane(cur ? cd.w : nd.w, uu);
           const int32_t kg = (int32_t)((uint32_t)dy >> 24);
           kmax = kg > kmax ? kg : kmax;
-          const bool mine = s == G;
+          const bool mine = grp == G;
           ao = mine ? make64(dx, dy & 0xffffff) : ao;
           bo = mine ? make64(dz, dw) : bo;
           k = mine ? kg : k;
@@ -721,16 +727,16 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
     const double* pb = P.Bv + bo + li;
 #pragma unroll
     for (int j = 0; j < QA; ++j)
-      if (li + 16 * j < mk) sa[d][j] = pa[16 * j];
+      if (li + GL * j < mk) sa[d][j] = pa[GL * j];
 #pragma unroll
     for (int j = 0; j < QB; ++j)
-      if (li + 16 * j < kn) sb[d][j] = pb[16 * j];
+      if (li + GL * j < kn) sb[d][j] = pb[GL * j];
   };
 
   // the step in the stage: its packed word and the lane's group's inner size
   int32_t stw = 0, stk = 0;
-  double* const As = wl + s * kGroup;
-  double* const Bs = As + kGroup / 2;
+  double* const As = wl + grp * kGroup;
+  double* const Bs = As + kA;
   auto stage_write = [&](auto slot) {
     constexpr int d = decltype(slot)::value;
     stw = sw[d];
@@ -740,27 +746,34 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
     // past the group's k (up to the step's largest) add nothing
     const int32_t kn = stk * n;
 #pragma unroll
-    for (int j = 0; j < QA; ++j) As[li + 16 * j] = sa[d][j];
+    for (int j = 0; j < QA; ++j) As[li + GL * j] = sa[d][j];
 #pragma unroll
-    for (int j = 0; j < QB; ++j) Bs[li + 16 * j] = li + 16 * j < kn ? sb[d][j] : 0.0;
+    for (int j = 0; j < QB; ++j) Bs[li + GL * j] = li + GL * j < kn ? sb[d][j] : 0.0;
   };
 
   double acc[V];
 #pragma unroll
   for (int x = 0; x < V; ++x) acc[x] = 0.0;
-  // Lane (g, rho, gam): A(2rho + i, t) = As[(2rho + i)*k + t], B(t, 2gam + j) = Bs[t*n + 2gam + j]
+  // Lane (s, rho, gam), inner index t = ks + KS*j: A(rho*RM + i, t) =
+  // As[(rho*RM + i)*k + t], B(t, gam*RN + jj) = Bs[t*n + gam*RN + jj] of its
+  // group's product.  Inner indices past the group's k (up to the step's
+  // largest, rounded up to KS) meet zero B rows.
   auto compute = [&]() {
     const int32_t n = (stw >> 5) & 31, kmax = (stw >> 10) & 31;
-    const double* Ar = As + 2 * rho * stk;
-    const double* Bc = Bs + 2 * gam;
-#pragma unroll 4
-    for (int32_t t = 0; t < kmax; ++t) {
-      const double a0 = Ar[t], a1 = Ar[stk + t];
-      const double b0 = Bc[t * n], b1 = Bc[t * n + 1];
-      acc[0] = fma(a0, b0, acc[0]);
-      acc[1] = fma(a0, b1, acc[1]);
-      acc[2] = fma(a1, b0, acc[2]);
-      acc[3] = fma(a1, b1, acc[3]);
+    const double* Ar = As + rho * RM * stk + ks;
+    const double* Bc = Bs + ks * n + gam * RN;
+    const int32_t steps = (kmax + KS - 1) / KS;
+#pragma unroll 2
+    for (int32_t j = 0; j < steps; ++j) {
+      double a[RM], b[RN];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) a[i] = Ar[i * stk + KS * j];
+#pragma unroll
+      for (int jj = 0; jj < RN; ++jj) b[jj] = Bc[KS * j * n + jj];
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < RN; ++jj) acc[i * RN + jj] = fma(a[i], b[jj], acc[i * RN + jj]);
     }
   };
 
@@ -786,27 +799,39 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
     const int64_t coff = make64(__builtin_amdgcn_readlane(fifo_co0, r), __builtin_amdgcn_readlane(fifo_co1, r));
     const int64_t oo = make64(__builtin_amdgcn_readlane(fifo_oo0, r), __builtin_amdgcn_readlane(fifo_oo1, r));
     wave_sync();  // every group has read the stage
-    // this lane's output is tile slot y = s (one of its group's 2x2)
-    {
-      const int y = s;
+    // this lane's outputs are tile slots y = (V/4)*s + x
+#pragma unroll
+    for (int x = 0; x < V / 4; ++x) {
+      const int y = (V / 4) * s + x;
       const int R = rho * RM + y / RN, Cc = gam * RN + y % RN;
-      if (R < m && Cc < n) tile[R * n + Cc] = P.alpha * acc[0];
+      if (R < m && Cc < n) tile[R * n + Cc] = P.alpha * acc[x];
     }
     wave_sync();
     const int32_t mnv = m * n;
     double* out = P.Cv + coff;
     if (oo >= 0) {
       const double* ov = P.Ov + oo;
-      const int e = lane < mnv ? lane : 0;
-      const double ol = ov[e];
-      if (lane < mnv) out[lane] = tile[lane] + P.beta * ol;
+      double ol[MP * NP / 64];
+#pragma unroll
+      for (int u = 0; u < MP * NP / 64; ++u) {
+        const int e = lane + 64 * u;
+        ol[u] = ov[e < mnv ? e : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < MP * NP / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < mnv) out[e] = tile[e] + P.beta * ol[u];
+      }
     } else {
-      if (lane < mnv) out[lane] = tile[lane];
+#pragma unroll
+      for (int u = 0; u < MP * NP / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < mnv) out[e] = tile[e];
+      }
     }
 #pragma unroll
     for (int x = 0; x < V; ++x) acc[x] = 0.0;
   };
-  static_assert(MP * NP == 64, "one output per lane after the group sum");
 
   // Prime: slots 0..D-1.  Step i (slot i mod D): write the slot into the
   // stage, refill it with step i+D, multiply; finish the C block if the step
@@ -833,8 +858,8 @@ __device__ __forceinline__ void small_quad(const SmallOps& P, double* __restrict
 // One persistent launch over every class: each wave runs its share of the
 // classes selected by `mask` (bit c = class c) in turn.  D0, D1, D2 are the
 // products in flight of the 8x8, 8x16 and 16x8 classes (16x16 always holds 2:
-// four 16x16 slots do not fit beside its accumulators); D0 = 1 selects the
-// four-products-per-step form of the 8x8 class.
+// four 16x16 slots do not fit beside its accumulators); 1 selects the form
+// with several products per step (four for 8x8, two for 8x16 and 16x8).
 template <int D0, int D1, int D2>
 __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
@@ -854,12 +879,22 @@ __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restri
   for (int x = 0; x < 5; ++x) b[x] = cls_start[x];
   if (mask & 1) {
     if constexpr (D0 == 1)
-      small_quad<1>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+      small_multi<8, 8, 4, 1>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
     else
       small_class<8, 8, D0>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
   }
-  if (mask & 2) small_class<8, 16, D1>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
-  if (mask & 4) small_class<16, 8, D2>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
+  if (mask & 2) {
+    if constexpr (D1 == 1)
+      small_multi<8, 16, 2, 1>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
+    else
+      small_class<8, 16, D1>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
+  }
+  if (mask & 4) {
+    if constexpr (D2 == 1)
+      small_multi<16, 8, 2, 1>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
+    else
+      small_class<16, 8, D2>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
+  }
   if (mask & 8) small_class<16, 16, 2>(P, wl, b[3], b[4], xcd, wpx, wix, lane);
 }
 
@@ -912,10 +947,10 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
 // Compiled pipeline variants, indexed by the tuner's variant number.
 using SmallKernel = void (*)(const double*, const double*, const double*, const int4*, const int32_t*,
                             const int64_t*, const int4*, double*, double, double, int32_t);
-constexpr SmallKernel kSmallKernels[] = {k_numeric_small<1, 2, 2>, k_numeric_small<4, 2, 2>, k_numeric_small<1, 4, 2>,
-                                         k_numeric_small<1, 2, 4>, k_numeric_small<1, 4, 4>, k_numeric_small<2, 2, 2>};
+constexpr SmallKernel kSmallKernels[] = {k_numeric_small<1, 1, 1>, k_numeric_small<1, 2, 2>, k_numeric_small<4, 2, 2>,
+                                         k_numeric_small<1, 1, 2>, k_numeric_small<1, 2, 1>, k_numeric_small<1, 4, 4>};
 
-constexpr int kSmallDepths[][4] = {{1, 2, 2, 2}, {4, 2, 2, 2}, {1, 4, 2, 2}, {1, 2, 4, 2}, {1, 4, 4, 2}, {2, 2, 2, 2}};
+constexpr int kSmallDepths[][4] = {{1, 1, 1, 2}, {1, 2, 2, 2}, {4, 2, 2, 2}, {1, 1, 2, 2}, {1, 2, 1, 2}, {1, 4, 4, 2}};
 static_assert(sizeof(kSmallKernels) / sizeof(kSmallKernels[0]) == kSmallVariants, "variant table");
 static_assert(sizeof(kSmallDepths) / sizeof(kSmallDepths[0]) == kSmallVariants, "variant table");
 
