@@ -97,6 +97,8 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
         w = W.block_stream(8000 + s, s, s, s, nblocks)
         dA, dB, dCin = (bsmm.Matrix.from_csr(x, stream) for x in (w.A, w.B, w.C_old))
         dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
+        # the autotuner picks the small-block variant for this edge (untimed)
+        variant = bsmm.bsmm_tune_small(1.0, dA.handle, dB.handle, 1.0, dCin.handle, dC.handle, 0.0, 2, stream)[0]
         for _ in range(warmup):
             bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC, 0.0, stream=stream)
         torch.cuda.synchronize()
@@ -110,7 +112,7 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
         st = bsmm.bsmm_stats(dC.handle)
         num_ms = ph["numeric"] / max(n, 1)
         flops = st["useful_flops"]
-        row = {"edge": s, "blocks": nblocks, "path": PATH_NAMES.get(st["path"], st["path"]),
+        row = {"edge": s, "blocks": nblocks, "path": PATH_NAMES.get(st["path"], st["path"]), "variant": variant,
                "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
                "numeric_ms": round(num_ms, 4), "numeric_gflops": round(flops / num_ms / 1e6, 1),
                "numeric_gbs": round(8 * 4 * s * s * nblocks / num_ms / 1e6, 1)}
