@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="molecules")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--chain-nmol", type=int, default=256,
+    ap.add_argument("--chain-nmol", type=int, default=512,
                     help="molecules of the sign chain (--workload chain)")
     ap.add_argument("--chain-replays", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",

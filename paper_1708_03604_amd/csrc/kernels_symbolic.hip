@@ -283,18 +283,22 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
   }
 }
 
-// Large form: the longer rows (and rows beyond the limits, which it reports),
-// found 256 rows at a time as in the fill pass.
+// Large form: the longer rows (and rows beyond the limits, which it reports).
+// Workgroup w of G owns rows w, w+G, w+2G, ...; it looks at 256 of them at a
+// time, one per thread, and counts the long ones in turn, so long rows spread
+// over the whole grid while short ones cost one load each.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
   __shared__ CountShared<kMaxRowA> sh;
   __shared__ int32_t rows[kSymThreads];
   __shared__ int32_t nrows;
   const int tid = threadIdx.x;
-  for (int32_t base = blockIdx.x * kSymThreads; base < g.A.nbrows; base += gridDim.x * kSymThreads) {
+  const int64_t G = gridDim.x;
+  for (int64_t i0 = blockIdx.x; i0 < g.A.nbrows; i0 += G * kSymThreads) {
     if (tid == 0) nrows = 0;
     __syncthreads();
-    const int32_t i = base + tid;
-    if (i < g.A.nbrows && g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA) rows[atomicAdd(&nrows, 1)] = i;
+    const int64_t i = i0 + G * tid;
+    if (i < g.A.nbrows && g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA)
+      rows[atomicAdd(&nrows, 1)] = (int32_t)i;
     __syncthreads();
     const int32_t n = nrows;
     for (int32_t x = 0; x < n; ++x) count_row<kMaxRowA>(g, rows[x], sh);
@@ -610,19 +614,21 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_small(SymArgs g) {
   }
 }
 
-// Large form: the remaining rows.  Each workgroup looks at 256 rows at a time,
-// one per thread, lists the ones the small form leaves and fills them in turn.
+// Large form: the remaining rows, found as in the count pass (workgroup w of
+// G looks at rows w, w+G, ... 256 at a time and fills the ones the small
+// form leaves).
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
   __shared__ FillShared<FillLarge> sh;
   __shared__ int32_t rows[kSymThreads];
   __shared__ int32_t nrows;
   if (g.totals[kTotAbort]) return;
   const int tid = threadIdx.x;
-  for (int32_t base = blockIdx.x * kSymThreads; base < g.A.nbrows; base += gridDim.x * kSymThreads) {
+  const int64_t G = gridDim.x;
+  for (int64_t i0 = blockIdx.x; i0 < g.A.nbrows; i0 += G * kSymThreads) {
     if (tid == 0) nrows = 0;
     __syncthreads();
-    const int32_t i = base + tid;
-    if (i < g.A.nbrows && !fill_fits_small(g, i)) rows[atomicAdd(&nrows, 1)] = i;
+    const int64_t i = i0 + G * tid;
+    if (i < g.A.nbrows && !fill_fits_small(g, (int32_t)i)) rows[atomicAdd(&nrows, 1)] = (int32_t)i;
     __syncthreads();
     const int32_t n = nrows;
     for (int32_t x = 0; x < n; ++x) {
@@ -638,8 +644,7 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_sym_count_small, dim3(grid), dim3(kSymThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int batches = (a.A.nbrows + kSymThreads - 1) / kSymThreads;
-  hipLaunchKernelGGL(k_sym_count_large, dim3(batches < 512 ? batches : 512), dim3(kSymThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sym_count_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -649,8 +654,7 @@ hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_sym_fill_small, dim3(grid), dim3(kSymThreads), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int batches = (a.A.nbrows + kSymThreads - 1) / kSymThreads;
-  hipLaunchKernelGGL(k_sym_fill_large, dim3(batches < 512 ? batches : 512), dim3(kSymThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 
