@@ -54,27 +54,32 @@ constexpr int kXcds = 8;
 constexpr int kChunk = 16;
 
 // First stored position (within a part of n entries) of wave w's entries.
+// Parts hold fewer than 2^31 entries (C has fewer than 2^31 blocks), so the
+// arithmetic is 32-bit: divisions by the run-time wave count stay cheap.
 __device__ __forceinline__ int64_t wave_base(int64_t n, int32_t wpx, int32_t w) {
-  const int64_t nch = (n + kChunk - 1) / kChunk;
-  const int64_t chunks = (nch / wpx) * w + min<int64_t>(nch % wpx, w);
-  int64_t e = chunks * kChunk;
-  const int64_t last = nch - 1;  // the only chunk that may be short
-  if (nch > 0 && (last % wpx) < w) e -= nch * kChunk - n;
-  return e;
+  const uint32_t n32 = (uint32_t)n, wp = (uint32_t)wpx, w32 = (uint32_t)w;
+  const uint32_t nch = (n32 + kChunk - 1) / kChunk;
+  const uint32_t q = nch / wp, r = nch - q * wp;
+  const uint32_t chunks = q * w32 + (r < w32 ? r : w32);
+  uint32_t e = chunks * kChunk;
+  // the last chunk is the only one that may be short
+  if (nch > 0 && (nch - 1) % wp < w32) e -= nch * kChunk - n32;
+  return (int64_t)e;
 }
 
 // Stored position of the t-th entry (natural order) of a part of n entries.
 __device__ __forceinline__ int64_t stored_pos(int64_t t, int64_t n, int32_t wpx) {
-  const int64_t c = t / kChunk, u = t - c * kChunk;
-  const int32_t w = (int32_t)(c % wpx);
-  return wave_base(n, wpx, w) + (c / wpx) * kChunk + u;
+  const uint32_t t32 = (uint32_t)t, wp = (uint32_t)wpx;
+  const uint32_t c = t32 / kChunk, u = t32 - c * kChunk;
+  const uint32_t cq = c / wp, w = c - cq * wp;
+  return wave_base(n, wpx, (int32_t)w) + (int64_t)cq * kChunk + u;
 }
 
 __device__ __forceinline__ int shape_class(const int32_t* __restrict__ c_col_idx,
                                            const int32_t* __restrict__ c_col_sizes,
                                            const int64_t* __restrict__ c_blk_off, int32_t c, int32_t* mn) {
   const int32_t n = c_col_sizes[c_col_idx[c]];
-  const int32_t m = (int32_t)((c_blk_off[c + 1] - c_blk_off[c]) / n);
+  const int32_t m = (int32_t)((uint32_t)(c_blk_off[c + 1] - c_blk_off[c]) / (uint32_t)n);
   *mn = m | (n << 8);
   return (m > 8 ? 2 : 0) + (n > 8 ? 1 : 0);
 }
@@ -201,13 +206,17 @@ __global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ 
     const int32_t e = e0 + g;
     if (e >= nnzc) continue;
     const int4 ent = list[2 * (int64_t)e];
-    const int32_t m = ent.x & 255;
+    const uint32_t m = (uint32_t)(ent.x & 255);
+    // k = (m*k) / m without a division per product: for m*k <= 256 and
+    // m <= 16, k = floor(m*k * ceil(2^16/m) / 2^16) exactly (the excess is at
+    // most 256 / 2^16 < 1)
+    const uint32_t inv = (65536u + m - 1u) / m;
     const int64_t q = qstart[e];
     for (int32_t l = l0; l < ent.z; l += 16) {
       const int64_t p = (int64_t)ent.y + l;
       const int32_t a = prod_a[p], b = prod_b[p];
       const int64_t ao = Aoff[a];
-      const int32_t k = (int32_t)((Aoff[a + 1] - ao) / m);
+      const int32_t k = (int32_t)(((uint32_t)(Aoff[a + 1] - ao) * inv) >> 16);
       const int64_t bo = Boff[b];
       desc[q + l] = make_int4((int32_t)(uint32_t)ao, (int32_t)((uint32_t)(ao >> 32) | ((uint32_t)k << 24)),
                               (int32_t)(uint32_t)bo, (int32_t)(uint32_t)(bo >> 32));
