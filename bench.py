@@ -166,10 +166,20 @@ def cpu_baseline(w, gpu_flops_per_step, target_s=12.0):
         if dt >= target_s or nrows >= w.A.nbrows or spent > 3 * target_s:
             break
         nrows = min(w.A.nbrows, max(nrows * 2, int(nrows * target_s / max(dt, 1e-3))))
+    runs = [dt]
+    if nrows >= w.A.nbrows and dt < target_s / 2:
+        # the whole workload is a short sample: repeat it for about target_s
+        # and take the median run
+        while sum(runs) < target_s and len(runs) < 200:
+            t0 = time.perf_counter()
+            oracle.multiply(w.alpha, Asub, w.B, w.beta, Csub, w.eps)
+            runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(rows)} of {w.A.nbrows} block rows (random, seed 123), same B and filter; "
-                      f"{flops / 1e9:.2f} GFLOP in {dt:.2f} s",
+                      f"{flops / 1e9:.2f} GFLOP in {dt:.2f} s (median of {len(runs)} runs, "
+                      f"{sum(runs):.1f} s of CPU work)",
             "seconds": dt}
 
 
