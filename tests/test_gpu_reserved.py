@@ -36,7 +36,7 @@ def rel_err(got, ref):
     return d / n if n > 0 else d
 
 
-def run(A, B, Co, alpha, beta, eps, reserve=None, in_place=False):
+def run(A, B, Co, alpha, beta, eps, reserve=None, in_place=False, prec=bsmm.BSMM_FP64):
     dA = bsmm.Matrix.from_csr(A)
     dB = bsmm.Matrix.from_csr(B)
     if in_place:
@@ -47,7 +47,7 @@ def run(A, B, Co, alpha, beta, eps, reserve=None, in_place=False):
         dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
     if reserve:
         bsmm.bsmm_reserve(dC.handle, *reserve)
-    bsmm.multiply(alpha, dA, dB, beta, dCin, dC, eps)
+    bsmm.multiply(alpha, dA, dB, beta, dCin, dC, eps, prec=prec)
     out = dC.to_host() + (dC.stack(), bsmm.bsmm_stats(dC.handle))
     for m in {id(x): x for x in (dA, dB, dCin, dC) if x is not None}.values():
         m.close()
@@ -58,6 +58,8 @@ CASES = {
     "b23": ([23] * 16, [23] * 16, [23] * 16),
     "b5_13": ([5, 13, 13, 5, 5, 13] * 4, [13, 5, 5, 13] * 5, [5, 13, 5] * 7),
     "b32": ([32] * 8, [32] * 8, [32] * 8),
+    "mixed_9_22_32": ([9, 22, 32] * 4, [22, 32, 9] * 4, [32, 9, 22] * 4),
+    "b6": ([6] * 30, [6] * 30, [6] * 30),
 }
 
 
@@ -75,6 +77,18 @@ def test_reserved_equals_synchronous(name, in_place):
     for r, g in zip(ref[:4], got[:4]):
         assert np.array_equal(r, g)
     assert ref[4] == got[4]
+
+
+def test_reserved_split_equals_synchronous():
+    sizes = [23] * 14
+    A = W.random_matrix(104, sizes, sizes, 0.35)
+    B = W.random_matrix(105, sizes, sizes, 0.35)
+    Co = W.random_matrix(106, sizes, sizes, 0.3)
+    ref = run(A, B, Co, 1.0, 1.0, 0.5, prec=bsmm.BSMM_SPLIT_BF16X3)
+    got = run(A, B, Co, 1.0, 1.0, 0.5, reserve=(14 * 14, (14 * 23) ** 2, 14 ** 3), prec=bsmm.BSMM_SPLIT_BF16X3)
+    for r, g in zip(ref[:4], got[:4]):
+        assert np.array_equal(r, g)
+    assert ref[4] == got[4] and got[4]["path"] == bsmm.BSMM_PATH_SPLIT23
 
 
 def test_reserved_overflow_is_reported_and_recoverable():
