@@ -16,7 +16,7 @@
  *   - a block product is performed only if the product of the two block norms
  *     exceeds a threshold: the on-the-fly filter (Section 2).
  *
- * Readings where the paper is silent (all stated again in the design doc):
+ * Readings where the paper is silent:
  *   - the block norm is the Frobenius norm;
  *   - its sum of squares runs in a fixed order so that the filter decision is
  *     reproducible bit for bit: 64 interleaved partial sums (element e goes to
