@@ -326,10 +326,14 @@ template <int HB, int RA, int RB, int CC>
 struct FillCaps {
   static constexpr int kBits = HB, kSlots = 1 << HB, kRowA = RA, kRowC = RB, kCand = CC;
   static_assert(kSlots <= 32767, "slots must fit in int16");
-  static_assert(RA % kSymThreads == 0 && RB % kSymThreads == 0, "row chunking");
+  static_assert((RA % kSymThreads == 0 || RA < kSymThreads) && RB % kSymThreads == 0, "row chunking");
   static_assert(2 * RB <= kSlots, "hash load at most one half");
 };
+using FillTiny = FillCaps<9, 128, 256, 4096>;
 using FillSmall = FillCaps<10, 256, 512, 4096>;
+struct FillNone {  // no form: no row fits
+  static constexpr int kRowA = -1, kRowC = -1;
+};
 using FillLarge = FillCaps<kHashBits, kMaxRowA, kMaxRowBlocks, 8192>;
 
 template <int RA>
@@ -340,14 +344,14 @@ __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, i
   *a0_out = a0;
   *na_out = nA;
   if (nA > RA) return -1;
-  constexpr int kPer = RA / kSymThreads;
+  constexpr int kPer = RA >= kSymThreads ? RA / kSymThreads : 1;
   int32_t len[kPer];
   int64_t mysum = 0;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int32_t p = tid * kPer + u;
     len[u] = 0;
-    if (p < nA) {
+    if (p < nA) {  // nA <= RA
       const int32_t k = g.A.col_idx[a0 + p];
       const int32_t qs = g.B.row_ptr[k];
       len[u] = g.B.row_ptr[k + 1] - qs;
@@ -598,18 +602,24 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
   }
 }
 
-__device__ __forceinline__ bool fill_fits_small(const SymArgs& g, int32_t i) {
-  return g.A.row_ptr[i + 1] - g.A.row_ptr[i] <= FillSmall::kRowA &&
-         g.c_row_ptr[i + 1] - g.c_row_ptr[i] <= FillSmall::kRowC;
+template <class Cap>
+__device__ __forceinline__ bool fill_fits(const SymArgs& g, int32_t i) {
+  return g.A.row_ptr[i + 1] - g.A.row_ptr[i] <= Cap::kRowA && g.c_row_ptr[i + 1] - g.c_row_ptr[i] <= Cap::kRowC;
 }
 
-// Small form: every row that fits its capacities, one workgroup per row.
-__global__ __launch_bounds__(kSymThreads) void k_sym_fill_small(SymArgs g) {
-  __shared__ FillShared<FillSmall> sh;
+__device__ __forceinline__ bool fill_fits_small(const SymArgs& g, int32_t i) { return fill_fits<FillSmall>(g, i); }
+
+// Small forms, one workgroup per row: form Cap takes the rows that fit it but
+// not the next smaller form Below (tiny: 21 KB of LDS, seven workgroups per
+// CU; small: 34 KB, four).
+template <class Cap, class Below>
+__global__ __launch_bounds__(kSymThreads) void k_sym_fill_form(SymArgs g) {
+  __shared__ FillShared<Cap> sh;
   if (g.totals[kTotAbort]) return;
   for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
-    if (!fill_fits_small(g, i)) continue;  // uniform: every thread reads the same sizes
-    fill_row<FillSmall>(g, i, sh);
+    // uniform: every thread reads the same sizes
+    if (!fill_fits<Cap>(g, i) || fill_fits<Below>(g, i)) continue;
+    fill_row<Cap>(g, i, sh);
     __syncthreads();
   }
 }
@@ -651,8 +661,11 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
 hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
-  hipLaunchKernelGGL(k_sym_fill_small, dim3(grid), dim3(kSymThreads), 0, s, a);
+  hipLaunchKernelGGL((k_sym_fill_form<FillTiny, FillNone>), dim3(grid), dim3(kSymThreads), 0, s, a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sym_fill_form<FillSmall, FillTiny>), dim3(grid), dim3(kSymThreads), 0, s, a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();

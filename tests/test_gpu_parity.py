@@ -352,12 +352,17 @@ def _rows_dense_mask(seed, nr, nc, dense_rows, p):
     return mask
 
 
-@pytest.mark.parametrize("case", ["long_a_rows", "wide_c_rows"])
+@pytest.mark.parametrize("case", ["long_a_rows", "wide_c_rows", "medium_rows"])
 def test_fill_both_forms(case):
-    # Rows beyond the small fill form (more than 256 A blocks, or more than
-    # 512 result blocks) run in the large form; the others in the small one,
-    # in the same multiply.
-    if case == "long_a_rows":
+    # The fill runs in three forms by row size: tiny (at most 128 A blocks and
+    # 256 result blocks), small (256 and 512) and large (the rest, up to the
+    # limits); rows of several forms meet in one multiply.
+    if case == "medium_rows":
+        nr, nk, nc = 24, 300, 450
+        ma = _rows_dense_mask(507, nr, nk, [], 0.05)
+        ma[[2, 9], :200] = True
+        mb = _rows_dense_mask(508, nk, nc, [], 0.02)
+    elif case == "long_a_rows":
         nr, nk, nc = 24, 600, 40
         ma = _rows_dense_mask(501, nr, nk, [0, 7, 23], 0.05)
         mb = _rows_dense_mask(502, nk, nc, [], 0.3)
@@ -377,6 +382,8 @@ def test_fill_both_forms(case):
     ref = oracle.multiply(1.0, A, B, 0.0, None, 0.0)
     nA = np.diff(A.row_ptr)
     nC = np.diff(ref.row_ptr)
-    assert (nA > 256).any() or (nC > 512).any()
-    assert ((nA <= 256) & (nC <= 512)).any()
+    tiny = (nA <= 128) & (nC <= 256)
+    small = (nA <= 256) & (nC <= 512) & ~tiny
+    large = ~tiny & ~small
+    assert tiny.any() and (small.any() if case == "medium_rows" else large.any())
     check(ref, gpu_multiply(A, B, None, 1.0, 0.0, 0.0), exact=True)
