@@ -195,7 +195,8 @@ bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
  *                 (then nothing is timed and the table is unchanged)
  *   ms_out      : NULL, or host array [BSMM_SMALL_VARIANTS * 4] receiving
  *                 the milliseconds of variant v, class c at [4*v + c],
- *                 summed over the reps
+ *                 summed over the reps (0 for a variant that does not serve
+ *                 these block edges)
  * C_in must not be C_out (BSMM_E_ARG), and C_out must not be reserved.
  * Synchronises `stream`.
  */
@@ -205,7 +206,9 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
 /* Products kept in flight per wave by variant v in the classes 8x8, 8x16,
  * 16x8 and 16x16 (rows x columns) into depths[4]; 1 means several products
  * of one C block per step (four for 8x8, one per 16-lane group; two for 8x16
- * and 16x8, one per 32-lane group).  BSMM_E_ARG if v is out of range. */
+ * and 16x8, one per 32-lane group); 8 means two such steps of the 8x8 class
+ * in flight, which only serves block edges of at most 8 (multiplies with
+ * larger edges use variant 1 instead).  BSMM_E_ARG if v is out of range. */
 bsmm_status bsmm_small_variant(int32_t v, int32_t* depths);
 
 /* Tuning key of the product A*B: bits e-1, 16+e-1 and 32+e-1 are set for each

@@ -713,6 +713,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     HIP_TRY(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
     variant = tuned_variant(tune_key(A, B));
+    if (std::max(A->max_edge, B->max_edge) > small_variant_max_edge(variant)) variant = kSmallDefault;
     HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, variant,
                                  kSmallAllClasses, s));
     C->small_args = na;
@@ -919,8 +920,13 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
   HIP_TRY(hipEventCreate(&ev.e[0]));
   HIP_TRY(hipEventCreate(&ev.e[1]));
   double total[kSmallVariants];
+  const int32_t edge = std::max(A->max_edge, B->max_edge);
   for (int32_t v = 0; v < kSmallVariants; ++v) {
     total[v] = 0.0;
+    if (edge > small_variant_max_edge(v)) {  // not valid for these sizes: not timed
+      total[v] = HUGE_VAL;
+      continue;
+    }
     for (int c = 0; c < 4; ++c) {
       HIP_TRY(hipEventRecord(ev.e[0], s));
       for (int32_t r = 0; r < reps; ++r)
@@ -934,8 +940,8 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
       if (ms_out) ms_out[4 * v + c] = ms;
     }
   }
-  int32_t best = 0;
-  for (int32_t v = 1; v < kSmallVariants; ++v)
+  int32_t best = kSmallDefault;
+  for (int32_t v = 0; v < kSmallVariants; ++v)
     if (total[v] < total[best]) best = v;
   HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, best,
                                kSmallAllClasses, s));

@@ -151,13 +151,17 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
                               int32_t* cls_start, int64_t* cnp, int64_t* qstart, int4* desc, hipStream_t s);
 // Pipeline variants of the small-block kernel: variant v keeps
 // small_variant_depths(v)[c] products in flight in class c (1 means the
-// form with several products per step: four for 8x8, two for 8x16, 16x8).  `mask` selects
+// form with several products per step: four for 8x8, two for 8x16, 16x8;
+// 8 means two such steps of the 8x8 class, for block edges of at most 8).  `mask` selects
 // the classes to run (bit c = class c): all of them in a multiply, one at a
 // time when tuning.  kSmallDefault is the untuned choice.
 constexpr int32_t kSmallVariants = 6;
 constexpr int32_t kSmallDefault = 1;  // 8x8 class four products per step, 2 in flight for the others
 constexpr int32_t kSmallAllClasses = 15;
 void small_variant_depths(int32_t v, int32_t* depths);
+// Largest block edge variant v serves (8 for the variant that keeps two steps
+// of four 8x8 products in flight; multiplies with larger edges use the default).
+int32_t small_variant_max_edge(int32_t v);
 hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_t* cls_start, const int64_t* qstart,
                                 const int4* desc, int32_t variant, int32_t mask, hipStream_t s);
 

@@ -588,13 +588,15 @@ __device__ __forceinline__ void small_class(const SmallOps& P, double* __restric
 //
 // One LDS stage (each group: A then B; the tile of a finished block is
 // parked there too) and D register slots of PG products.
-template <int MP, int NP, int PG, int D>
+// KM bounds the inner size k (16 in general; 8 lets two steps of the 8x8
+// class fit in registers when every block edge is at most 8).
+template <int MP, int NP, int PG, int D, int KM = 16>
 __device__ __forceinline__ void small_multi(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
                                             int32_t xcd, int32_t wpx, int32_t wix, int lane) {
   constexpr int RM = MP / 4, RN = NP / 4, V = RM * RN;
   constexpr int GL = 64 / PG;                      // lanes per group
   constexpr int KS = 4 / PG;                       // K slices per product
-  constexpr int kA = MP * 16, kB = 16 * NP;        // largest A and B blocks (k = 16)
+  constexpr int kA = MP * KM, kB = KM * NP;        // largest A and B blocks
   constexpr int QA = kA / GL, QB = kB / GL;        // loads per lane of a group
   constexpr int kGroup = kA + kB;                  // LDS doubles per group: A, then B
   static_assert(PG * kGroup <= 2 * kStage, "one stage of PG groups fits the wave's LDS");
@@ -868,7 +870,8 @@ __device__ __forceinline__ void small_multi(const SmallOps& P, double* __restric
 // classes selected by `mask` (bit c = class c) in turn.  D0, D1, D2 are the
 // products in flight of the 8x8, 8x16 and 16x8 classes (16x16 always holds 2:
 // four 16x16 slots do not fit beside its accumulators); 1 selects the form
-// with several products per step (four for 8x8, two for 8x16 and 16x8).
+// with several products per step (four for 8x8, two for 8x16 and 16x8), and
+// D0 = 8 two steps of four 8x8 products for block edges of at most 8.
 template <int D0, int D1, int D2>
 __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restrict__ Av, const double* __restrict__ Bv,
                                                        const double* __restrict__ Ov, const int4* __restrict__ list,
@@ -889,6 +892,8 @@ __global__ __launch_bounds__(256, 4) void k_numeric_small(const double* __restri
   if (mask & 1) {
     if constexpr (D0 == 1)
       small_multi<8, 8, 4, 1>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+    else if constexpr (D0 == 8)
+      small_multi<8, 8, 4, 2, 8>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
     else
       small_class<8, 8, D0>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
   }
@@ -957,11 +962,13 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
 using SmallKernel = void (*)(const double*, const double*, const double*, const int4*, const int32_t*,
                             const int64_t*, const int4*, double*, double, double, int32_t);
 constexpr SmallKernel kSmallKernels[] = {k_numeric_small<1, 1, 1>, k_numeric_small<1, 2, 2>, k_numeric_small<4, 2, 2>,
-                                         k_numeric_small<1, 1, 2>, k_numeric_small<1, 2, 1>, k_numeric_small<1, 4, 4>};
+                                         k_numeric_small<1, 1, 2>, k_numeric_small<1, 2, 1>, k_numeric_small<8, 2, 2>};
 
-constexpr int kSmallDepths[][4] = {{1, 1, 1, 2}, {1, 2, 2, 2}, {4, 2, 2, 2}, {1, 1, 2, 2}, {1, 2, 1, 2}, {1, 4, 4, 2}};
+constexpr int kSmallDepths[][4] = {{1, 1, 1, 2}, {1, 2, 2, 2}, {4, 2, 2, 2}, {1, 1, 2, 2}, {1, 2, 1, 2}, {8, 2, 2, 2}};
 static_assert(sizeof(kSmallKernels) / sizeof(kSmallKernels[0]) == kSmallVariants, "variant table");
 static_assert(sizeof(kSmallDepths) / sizeof(kSmallDepths[0]) == kSmallVariants, "variant table");
+
+int32_t small_variant_max_edge(int32_t v) { return v >= 0 && v < kSmallVariants && kSmallDepths[v][0] == 8 ? 8 : 16; }
 
 void small_variant_depths(int32_t v, int32_t* depths) {
   for (int c = 0; c < 4; ++c) depths[c] = (v >= 0 && v < kSmallVariants) ? kSmallDepths[v][c] : 0;

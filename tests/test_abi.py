@@ -62,7 +62,7 @@ def test_tuning_table_without_device():
     assert len(set(map(tuple, depths))) == bsmm.BSMM_SMALL_VARIANTS
     assert depths[1] == [1, 2, 2, 2]  # the untuned choice
     for d in depths:
-        assert d[0] in (1, 4) and d[1] in (1, 2, 4) and d[2] in (1, 2, 4) and d[3] == 2
+        assert d[0] in (1, 4, 8) and d[1] in (1, 2, 4) and d[2] in (1, 2, 4) and d[3] == 2
     with pytest.raises(bsmm.BsmmError):
         bsmm.bsmm_small_variant(bsmm.BSMM_SMALL_VARIANTS)
     key = tune.edges_key([5, 13], [13], [1, 16])

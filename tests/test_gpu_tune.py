@@ -64,21 +64,51 @@ def test_variants_of_one_form_give_the_same_bits(table):
     key = bsmm.bsmm_tune_key(dA.handle, dB.handle)
     first = {}
     for v in range(bsmm.BSMM_SMALL_VARIANTS):
-        form = tuple(x == 1 for x in bsmm.bsmm_small_variant(v)[:3])
         bsmm.bsmm_tune_set(key, v)
         dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
         bsmm.multiply(0.75, dA, dB, -0.5, dCin, dC, 0.0)
         s = bsmm.bsmm_stats(dC.handle)
-        assert s["path"] == bsmm.BSMM_PATH_SMALL and s["variant"] == v
+        # the variant for block edges of at most 8 falls back to variant 1 here
+        used = 1 if bsmm.bsmm_small_variant(v)[0] == 8 else v
+        assert s["path"] == bsmm.BSMM_PATH_SMALL and s["variant"] == used
         rp, ci, vals = dC.to_host()
         assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx)
         assert rel_err(vals, ref.values) <= REL_TOL
+        form = tuple(x in (1, 8) for x in bsmm.bsmm_small_variant(used)[:3])
         if form not in first:
             first[form] = (v, vals)
         else:
             assert np.array_equal(vals, first[form][1]), f"variant {v} differs from variant {first[form][0]}"
         dC.close()
     assert len(first) >= 3  # several combinations of forms were run
+    for m in (dA, dB, dCin):
+        m.close()
+
+
+def test_variant_for_edges_up_to_8(table):
+    # two steps of four 8x8 products in flight: only for block edges <= 8
+    rs, ks, cs = [3, 8, 1, 5, 6] * 5, [8, 2, 7, 4] * 6, [6, 8, 3] * 7
+    A = W.random_matrix(431, rs, ks, 0.4)
+    B = W.random_matrix(432, ks, cs, 0.4)
+    Co = W.random_matrix(433, rs, cs, 0.3)
+    ref = oracle.multiply(1.25, A, B, 0.5, Co, 0.0)
+    dA, dB, dCin = bsmm.Matrix.from_csr(A), bsmm.Matrix.from_csr(B), bsmm.Matrix.from_csr(Co)
+    key = bsmm.bsmm_tune_key(dA.handle, dB.handle)
+    lite = [v for v in range(bsmm.BSMM_SMALL_VARIANTS) if bsmm.bsmm_small_variant(v)[0] == 8]
+    assert lite
+    vals = {}
+    for v in lite + [0]:
+        bsmm.bsmm_tune_set(key, v)
+        dC = bsmm.Matrix.empty(A.row_sizes, B.col_sizes)
+        bsmm.multiply(1.25, dA, dB, 0.5, dCin, dC, 0.0)
+        assert bsmm.bsmm_stats(dC.handle)["variant"] == v
+        rp, ci, vals[v] = dC.to_host()
+        assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx)
+        assert rel_err(vals[v], ref.values) <= REL_TOL
+        dC.close()
+    # every C block is in the 8x8 class, which both variants run four products
+    # per step: same operations, same bits
+    assert all(np.array_equal(vals[v], vals[0]) for v in lite)
     for m in (dA, dB, dCin):
         m.close()
 
@@ -96,7 +126,10 @@ def test_tuner_result_and_table(table):
     assert entry["depths"] == bsmm.bsmm_small_variant(v)
     assert tune.edges_key(entry["rows"], entry["inner"], entry["cols"]) == key
     ms = np.array(entry["ms"])
-    assert ms.shape == (bsmm.BSMM_SMALL_VARIANTS, 4) and np.all(ms > 0)
+    assert ms.shape == (bsmm.BSMM_SMALL_VARIANTS, 4)
+    for u in range(bsmm.BSMM_SMALL_VARIANTS):
+        # the variant for block edges of at most 8 is not timed for these sizes
+        assert np.all(ms[u] == 0) if bsmm.bsmm_small_variant(u)[0] == 8 else np.all(ms[u] > 0)
     assert bsmm.bsmm_tune_get(key) == v
     assert bsmm.bsmm_stats(dC.handle)["variant"] == v
     rp, ci, vals = dC.to_host()
