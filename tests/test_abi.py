@@ -96,3 +96,23 @@ def test_saved_tuning_table():
         assert 0 <= e["variant"] < bsmm.BSMM_SMALL_VARIANTS
         assert e["depths"] == bsmm.bsmm_small_variant(e["variant"])
         assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variant"]
+
+
+def test_tuning_table_json_roundtrip(tmp_path):
+    from paper_1708_03604_amd import tune
+    bsmm.lib()
+    saved = bsmm.bsmm_tune_entries()
+    entries = [{"rows": [5, 13], "inner": [5, 13], "cols": [5, 13], "variant": 3, "depths": bsmm.bsmm_small_variant(3)},
+               {"rows": [2], "inner": [7, 8], "cols": [1, 16], "variant": 0, "depths": bsmm.bsmm_small_variant(0)}]
+    path = str(tmp_path / "table.json")
+    try:
+        tune.save(entries, path, note="test")
+        loaded = tune.load(path)
+        assert loaded == entries
+        for e in entries:
+            assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variant"]
+    finally:
+        for k in bsmm.bsmm_tune_entries():
+            bsmm.bsmm_tune_set(k, -1)
+        for k, v in saved.items():
+            bsmm.bsmm_tune_set(k, v)
