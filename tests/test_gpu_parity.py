@@ -215,6 +215,25 @@ def test_empty_and_degenerate():
     check(ref, gpu_multiply(A, B, None, 1.0, 0.0, 0.0))
 
 
+@pytest.mark.parametrize("edges", [[5, 13], [9, 22, 32], [6]])
+def test_degenerate_on_every_path(edges):
+    # the small-block and tiled paths on the same degenerate inputs
+    rs = np.resize(np.array(edges, dtype=np.int32), 4)
+    A0 = W.with_pattern(rs, rs[:3], [0, 0, 0, 0, 0], [])
+    B = W.random_matrix(86, rs[:3], rs, 1.0)
+    Co = W.random_matrix(87, rs, rs, 0.5)
+    # no A blocks, beta = 0: empty result
+    check(oracle.multiply(1.0, A0, B, 0.0, None, 0.0), gpu_multiply(A0, B, None, 1.0, 0.0, 0.0))
+    # no products but beta != 0: beta * C_in
+    check(oracle.multiply(1.0, A0, B, -2.0, Co, 0.0), gpu_multiply(A0, B, Co, 1.0, -2.0, 0.0))
+    # the filter drops every product; C_in's pattern stays
+    A = W.random_matrix(88, rs, rs[:3], 1.0)
+    check(oracle.multiply(1.0, A, B, 0.5, Co, 1e30), gpu_multiply(A, B, Co, 1.0, 0.5, 1e30))
+    # a single block
+    A1 = W.random_matrix(89, rs[:1], rs[:1], 1.0)
+    check(oracle.multiply(1.0, A1, A1, 0.0, None, 0.0), gpu_multiply(A1, A1, None, 1.0, 0.0, 0.0))
+
+
 def test_error_paths():
     sizes = [23] * 4
     A = bsmm.Matrix.from_csr(W.random_matrix(91, sizes, sizes, 0.5))
