@@ -255,15 +255,17 @@ def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_
             "note": "numeric_ms includes splitting A and B into BF16 terms"}
 
 
-def chain_leg(nmol, steps=12, eps=1e-7, replays=3):
+def chain_leg(nmol, steps=12, eps=1e-7, replays=3, prec=None):
     """Newton-Schulz sign chain (12 steps, filter 1e-7) on a symmetric,
     Gershgorin-scaled molecule matrix, captured in one HIP graph; returns the
-    graph replay throughput and the FP64 residual."""
-    import torch
+    graph replay throughput and the FP64 residual, and the open chain (its
+    final X stays on the device for comparison)."""
+    from paper_1708_03604_amd import bsmm
     from paper_1708_03604_amd import workloads as W
     from paper_1708_03604_amd.chain import SignChain
+    prec = bsmm.BSMM_FP64 if prec is None else prec
     X0, info = W.symmetric_scaled(nmol=nmol)
-    ch = SignChain(X0, steps=steps, eps=eps)
+    ch = SignChain(X0, steps=steps, eps=eps, prec=prec)
     flops, prods, blocks = ch.count_flops()
     # the same chain enqueued call by call (no graph), for comparison
     t0 = time.perf_counter()
@@ -286,8 +288,26 @@ def chain_leg(nmol, steps=12, eps=1e-7, replays=3):
            "useful_gflop_per_chain": round(flops / 1e9, 3), "products_per_chain": int(prods),
            "x_blocks_per_step": blocks, "residual_fro": res,
            "residual_rel": res / math.sqrt(n), "replays": replays, "ms_per_chain_eager": round(dt_eager * 1e3, 3)}
-    ch.close()
-    return out
+    return out, ch
+
+
+def chain_difference(ch_split, ch_fp64):
+    """||X_split - X_fp64||_F / ||X_fp64||_F of the two chains' final X, on the
+    device: D = 1 * X_split * I - 1 * X_fp64 (an FP64 multiply by the identity)."""
+    import torch
+    from paper_1708_03604_amd import bsmm
+    ch_split.stream.synchronize()
+    ch_fp64.stream.synchronize()
+    xs, xf = ch_split.final, ch_fp64.final
+    D = bsmm.Matrix.empty(xs.row_sizes, xs.col_sizes)
+    bsmm.multiply(1.0, xs, ch_split.I1, -1.0, xf, D, 0.0)
+    t = torch.zeros(2, dtype=torch.float64, device="cuda")
+    bsmm.bsmm_frobenius(D.handle, t[0:1], None)
+    bsmm.bsmm_frobenius(xf.handle, t[1:2], None)
+    torch.cuda.synchronize()
+    d, ref = (float(x) for x in t.cpu())
+    D.close()
+    return d / ref if ref > 0 else d
 
 
 def main():
@@ -325,13 +345,23 @@ def main():
     if args.workload == "chain":
         torch.cuda.set_device(0)
         log(f"[bench] sign chain on {args.chain_nmol} molecules")
-        ch = chain_leg(args.chain_nmol, replays=args.chain_replays)
+        ch, chain_f = chain_leg(args.chain_nmol, replays=args.chain_replays)
         out = {"metric": "useful GFLOP/s of the Newton-Schulz sign chain (block-sparse 23x23 FP64 multiplies, "
                          "one HIP graph)",
                "value": ch.pop("value"), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.chain_replays, "warmup": 1,
                "ms_per_step": ch["ms_per_chain"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                "dtype": "f64", "data": "synthetic", "config": {"workload": ch.pop("workload")}, "chain": ch}
         log(f"[bench] chain: {ch['ms_per_chain']} ms, {out['value']} GFLOP/s, residual {ch['residual_fro']:.3e}")
+        log("[bench] the same chain with split-precision iteration multiplies (residual in FP64)")
+        sp, chain_s = chain_leg(args.chain_nmol, replays=args.chain_replays, prec=bsmm.BSMM_SPLIT_BF16X3)
+        sp.pop("workload")
+        sp["speedup_vs_fp64"] = round(ch["ms_per_chain"] / sp["ms_per_chain"], 3)
+        sp["x_rel_fro_diff_vs_fp64"] = chain_difference(chain_s, chain_f)
+        out["chain_split_bf16x3"] = sp
+        log(f"[bench] split chain: {sp['ms_per_chain']} ms ({sp['speedup_vs_fp64']}x), residual "
+            f"{sp['residual_fro']:.3e}, final X differs from the FP64 chain's by {sp['x_rel_fro_diff_vs_fp64']:.2e}")
+        chain_s.close()
+        chain_f.close()
         print(json.dumps(out), flush=True)
         return
     if args.workload == "sweep":

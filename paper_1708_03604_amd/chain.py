@@ -9,7 +9,8 @@ Newton-Schulz iteration for sign(X0),
     X_{k+1} = 1/2 X_k T_k
 
 with the on-the-fly filter in every multiply and a filter of every result at
-the same threshold, then the residual ||X X - I||_F.  All multiplies write
+the same threshold, then the residual ||X X - I||_F (always in FP64; the
+iteration's multiplies may run in split precision).  All multiplies write
 reserved (device-sized) matrices, so the whole sequence runs without a host
 synchronisation and can be captured once in a HIP graph and replayed.
 
@@ -34,13 +35,16 @@ class SignChain:
     X0 (host BlockCSR, square, symmetric, spectral radius < 1) is uploaded
     once and never written, so every run starts from it.  `caps` =
     (max blocks, max values, max products per multiply) of the reserved work
-    matrices (default: dense).
+    matrices (default: dense).  `prec` is the precision of the iteration's
+    multiplies (bsmm.BSMM_FP64 or bsmm.BSMM_SPLIT_BF16X3); the residual
+    multiply is FP64.
     """
 
-    def __init__(self, X0, steps=12, eps=1e-7, caps=None, stream=None):
+    def __init__(self, X0, steps=12, eps=1e-7, caps=None, stream=None, prec=bsmm.BSMM_FP64):
         import torch
         self.steps = steps
         self.eps = eps
+        self.prec = prec
         self.stream = stream if stream is not None else torch.cuda.Stream()
         st = self.stream
         nnzb, nvals, nprod = caps if caps is not None else dense_caps(X0)
@@ -63,9 +67,9 @@ class SignChain:
         cur = self.X0
         for k in range(self.steps):
             nxt = self.X[k % 2]
-            bsmm.multiply(-1.0, cur, cur, 1.0, self.I3, self.T, self.eps, stream=st)
+            bsmm.multiply(-1.0, cur, cur, 1.0, self.I3, self.T, self.eps, prec=self.prec, stream=st)
             bsmm.bsmm_filter(self.T.handle, self.eps, st)
-            bsmm.multiply(0.5, cur, self.T, 0.0, None, nxt, self.eps, stream=st)
+            bsmm.multiply(0.5, cur, self.T, 0.0, None, nxt, self.eps, prec=self.prec, stream=st)
             bsmm.bsmm_filter(nxt.handle, self.eps, st)
             cur = nxt
         bsmm.multiply(1.0, cur, cur, -1.0, self.I1, self.R, 0.0, stream=st)
@@ -82,7 +86,7 @@ class SignChain:
         for k in range(self.steps):
             nxt = self.X[k % 2]
             for args in ((-1.0, cur, cur, 1.0, self.I3, self.T), (0.5, cur, self.T, 0.0, None, nxt)):
-                bsmm.multiply(*args, self.eps, stream=st)
+                bsmm.multiply(*args, self.eps, prec=self.prec, stream=st)
                 s = bsmm.bsmm_stats(args[5].handle)
                 flops += s["useful_flops"]
                 prods += s["products"]

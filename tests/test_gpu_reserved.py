@@ -187,3 +187,53 @@ def test_chain_graph_replays_match_eager():
         a = torch.randn(256, 256, device="cuda", dtype=torch.float64)
         (a @ a).sum().item()
     ch.close()
+
+
+def _dense(csr, sizes):
+    rp, ci, v = csr
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    n = int(off[-1])
+    out = np.zeros((n, n))
+    pos = 0
+    for i in range(len(sizes)):
+        for x in range(rp[i], rp[i + 1]):
+            j = ci[x]
+            m, k = sizes[i], sizes[j]
+            out[off[i]:off[i + 1], off[j]:off[j + 1]] = v[pos:pos + m * k].reshape(m, k)
+            pos += m * k
+    return out
+
+
+def test_chain_split_close_to_fp64():
+    """The chain with its iteration multiplies in split precision (three BF16
+    terms, FP32 accumulation per product) against the FP64 chain: the final X
+    within 1e-5 relative Frobenius (about 2^-24 per multiply, grown by up to
+    1.5x per step for eigenvalues near zero; patterns may differ where a block
+    norm sits at the filter threshold), the FP64 residual within 1e-5, and the
+    split chain's graph replays equal to its eager run bit for bit."""
+    import torch
+    from paper_1708_03604_amd.chain import SignChain
+    X0 = _chain_input(nmol=16, seed=5200)
+    sizes = np.asarray(X0.row_sizes)
+    dense, res = {}, {}
+    for prec in (bsmm.BSMM_FP64, bsmm.BSMM_SPLIT_BF16X3):
+        ch = SignChain(X0, steps=8, eps=1e-7, prec=prec)
+        ch.enqueue()
+        ch.stream.synchronize()
+        eager = ch.final.to_host()
+        dense[prec] = _dense(eager, sizes)
+        res[prec] = float(ch.residual.cpu()[0])
+        if prec == bsmm.BSMM_SPLIT_BF16X3:
+            ch.capture()
+            for rep in range(2):
+                ch.residual.zero_()
+                torch.cuda.synchronize()
+                ch.replay()
+                ch.stream.synchronize()
+                for x, y in zip(eager, ch.final.to_host()):
+                    assert np.array_equal(x, y), f"replay {rep}"
+                assert float(ch.residual.cpu()[0]) == res[prec]
+        ch.close()
+    f, s = dense[bsmm.BSMM_FP64], dense[bsmm.BSMM_SPLIT_BF16X3]
+    assert rel_err(s, f) <= 1e-5
+    assert abs(res[bsmm.BSMM_SPLIT_BF16X3] - res[bsmm.BSMM_FP64]) <= 1e-5 * res[bsmm.BSMM_FP64]
