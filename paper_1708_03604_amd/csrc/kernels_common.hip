@@ -22,7 +22,15 @@ __global__ __launch_bounds__(256) void k_block_norms(const int64_t* __restrict__
     const int64_t n = blk_off[b + 1] - o;
     const double* x = values + o;
     double p = 0.0;
-    for (int64_t e = lane; e < n; e += 64) p = fma(x[e], x[e], p);
+    // sixteen loads in flight (a 23x23 block in one round), then the FMAs in
+    // ascending e; elements past the block count as +0, which leaves p as is
+    for (int64_t e = lane; e < n; e += 16 * 64) {
+      double v[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v[t] = (e + 64 * t < n) ? x[e + 64 * t] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) p = fma(v[t], v[t], p);
+    }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       const double other = __shfl_down(p, d, 64);
