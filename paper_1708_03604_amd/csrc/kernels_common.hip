@@ -326,7 +326,15 @@ __global__ __launch_bounds__(256) void k_frob_partial(const double* __restrict__
   const int64_t b0 = per * blockIdx.x;
   const int64_t b1 = b0 + per < n ? b0 + per : n;
   double p = 0.0;
-  for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) p = fma(values[e], values[e], p);
+  // sixteen loads in flight, then the FMAs in ascending e (elements past the
+  // slice count as +0, which leaves p as is)
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += 16 * 256) {
+    double v[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = (e + 256 * t < b1) ? values[e + 256 * t] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) p = fma(v[t], v[t], p);
+  }
   const double t = block_tree_sum(p);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
