@@ -112,6 +112,7 @@ struct bsmm_matrix {
   DBuf<int64_t> rows[5], pre[5], scan_tmp, totals, fkeep, fvsz, fpos, fvoff;
   DBuf<uint32_t> flags;
   DBuf<int32_t> work;
+  DBuf<int32_t> wide;   // rows for the workgroup forms of the symbolic pass (count in flags[1])
   DBuf<int4> class_list;          // C blocks by padded shape class (small-block path), 2 per block
   DBuf<int4> prod_desc;           // per product operand offsets (small-block path)
   DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
@@ -382,6 +383,7 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->fvoff.release();
   m->flags.release();
   m->work.release();
+  m->wide.release();
   m->class_list.release();
   m->prod_desc.release();
   m->split_a.release();
@@ -553,12 +555,13 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // allocates or synchronises (graph-capturable); the bounds are capacities.
   const bool reserved = C->cap_nnzb > 0;
   // scratch
-  if (C->flags.ensure(1) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
+  if (C->flags.ensure(2) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
     if (C->rows[x].ensure(nbrows + 1) != hipSuccess || C->pre[x].ensure(nbrows + 1) != hipSuccess)
       return fail(BSMM_E_NOMEM, "scratch allocation failed");
+  if (C->wide.ensure(std::max(nbrows, 1)) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
   const double* normA = nullptr;
   const double* normB = nullptr;
   if (use_eps) {
@@ -576,7 +579,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       normB = C->norm_b.p;
     }
   }
-  HIP_TRY(launch_zero_u32(C->flags.p, 1, s));
+  HIP_TRY(launch_zero_u32(C->flags.p, 2, s));  // symbolic-pass flags and the wide-row count
   mark(C, ev, 1, s);
 
   SymArgs g{};
@@ -596,6 +599,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.row_ncand = C->rows[3].p;
   g.row_nf = C->rows[4].p;
   g.flags = C->flags.p;
+  g.wide = C->wide.p;
+  g.n_wide = reinterpret_cast<int32_t*>(C->flags.p + 1);
   g.totals = C->totals.p;
   HIP_TRY(launch_sym_count(g, s));
   {
@@ -815,7 +820,7 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
             m->class_pre.ensure(ncl) == hipSuccess && m->class_start.ensure(5) == hipSuccess &&
             m->class_np.ensure(nce) == hipSuccess && m->class_q.ensure(nce + 1) == hipSuccess &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
-            m->flags.ensure(1) == hipSuccess && m->work.ensure(1) == hipSuccess &&
+            m->flags.ensure(2) == hipSuccess && m->work.ensure(1) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&
             m->norm_self.ensure(cb) == hipSuccess && m->fkeep.ensure(cb + 1) == hipSuccess &&
             m->fvsz.ensure(cb + 1) == hipSuccess && m->fpos.ensure(cb + 1) == hipSuccess &&
@@ -823,6 +828,7 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
             m->split_b.ensure(split_elems(cb)) == hipSuccess;
   for (int x = 0; x < 5 && ok; ++x)
     ok = m->rows[x].ensure(nbrows + 1) == hipSuccess && m->pre[x].ensure(nbrows + 1) == hipSuccess;
+  ok = ok && m->wide.ensure(std::max(nbrows, 1)) == hipSuccess;
   if (!ok) return fail(BSMM_E_NOMEM, "device allocation for the reservation failed");
   // counters read back before the first reserved multiply: zero
   if (!m->has_stack) {

@@ -72,6 +72,10 @@ struct SymArgs {
   int64_t* row_ncand;
   int64_t* row_nf;     // m_i * sum over kept products of n_j * k
   uint32_t* flags;
+  // rows the one-thread (thin) path leaves to the workgroup forms, listed by
+  // the count pass in any order; *n_wide must be zero when the count pass starts
+  int32_t* wide;       // [nbrows]
+  int32_t* n_wide;
   // fill pass inputs/outputs (exclusive prefixes of the counts, length nbrows+1)
   const int32_t* c_row_ptr;
   const int64_t* row_pstart;

@@ -272,12 +272,189 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
   }
 }
 
+// ------------------------------------------------------------------ thin rows
+// Rows with at most kThinA stored A blocks, kThinT candidates and kThinO C_in
+// blocks (block-diagonal and nearly block-diagonal matrices: millions of rows
+// of one candidate each) are counted and filled by one thread each, with the
+// same results as the workgroup forms: columns ascending, a C block's products
+// in ascending A entry order.  The count pass lists every other row in
+// g.wide; the workgroup forms walk only that list.
+constexpr int kThinA = 4, kThinT = 8, kThinO = 8, kThinC = kThinT + kThinO;
+
+struct ThinRow {
+  int32_t a0, T, n, nc, o0, no;
+  int32_t cj[kThinT], cq[kThinT], cp[kThinT];  // kept candidates in order: column, B block, A entry
+  int32_t col[kThinC];                         // distinct columns, ascending
+  int32_t oj[kThinO];                          // C_in columns of the row
+  uint64_t nf;                                 // sum over kept candidates of n_j * k_p
+};
+
+// Element x of a register array by a run-time index (unrolled selects).
+template <int N, class T>
+__device__ __forceinline__ T thin_sel(const T (&a)[N], int x) {
+  T v = a[0];
+#pragma unroll
+  for (int y = 1; y < N; ++y) v = (x == y) ? a[y] : v;
+  return v;
+}
+
+// Add v to the ascending distinct list col[0..nc).
+__device__ __forceinline__ void thin_insert(ThinRow& r, int32_t v) {
+  bool dup = false;
+#pragma unroll
+  for (int x = 0; x < kThinC; ++x) dup = dup || (x < r.nc && r.col[x] == v);
+  if (dup) return;
+#pragma unroll
+  for (int x = 0; x < kThinC; ++x) {
+    if (x < r.nc && r.col[x] > v) {
+      const int32_t t = r.col[x];
+      r.col[x] = v;
+      v = t;
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < kThinC; ++x)
+    if (x == r.nc) r.col[x] = v;
+  ++r.nc;
+}
+
+// Load row i if it is thin; false (and nothing else done) if it is not.
+__device__ bool thin_load(const SymArgs& g, int32_t i, ThinRow& r) {
+  r.a0 = g.A.row_ptr[i];
+  const int32_t nA = g.A.row_ptr[i + 1] - r.a0;
+  if (nA > kThinA) return false;
+  int32_t qs[kThinA], pre[kThinA + 1], ks[kThinA];
+  double nrm[kThinA];
+  pre[0] = 0;
+#pragma unroll
+  for (int p = 0; p < kThinA; ++p) {
+    qs[p] = 0;
+    ks[p] = 0;
+    nrm[p] = 0.0;
+    int32_t len = 0;
+    if (p < nA) {
+      const int32_t k = g.A.col_idx[r.a0 + p];
+      qs[p] = g.B.row_ptr[k];
+      len = g.B.row_ptr[k + 1] - qs[p];
+      ks[p] = g.A.col_sizes[k];
+      nrm[p] = g.use_eps ? g.normA[r.a0 + p] : 0.0;
+    }
+    pre[p + 1] = pre[p] + len;
+  }
+  r.T = pre[kThinA];
+  if (r.T > kThinT) return false;
+  r.o0 = 0;
+  r.no = 0;
+  if (g.use_old) {
+    r.o0 = g.Cin.row_ptr[i];
+    r.no = g.Cin.row_ptr[i + 1] - r.o0;
+    if (r.no > kThinO) return false;
+  }
+  r.n = 0;
+  r.nc = 0;
+  r.nf = 0;
+#pragma unroll
+  for (int t = 0; t < kThinT; ++t) {
+    if (t < r.T) {
+      int p = 0;
+#pragma unroll
+      for (int x = 1; x < kThinA; ++x) p += (pre[x] <= t) ? 1 : 0;  // pre is non-decreasing
+      const int32_t q = thin_sel(qs, p) + (t - thin_sel(pre, p));
+      const bool keep = !g.use_eps || thin_sel(nrm, p) * g.normB[q] > g.eps;
+      if (keep) {
+        const int32_t j = g.B.col_idx[q];
+#pragma unroll
+        for (int x = 0; x < kThinT; ++x) {
+          if (x == r.n) {
+            r.cj[x] = j;
+            r.cq[x] = q;
+            r.cp[x] = p;
+          }
+        }
+        ++r.n;
+        r.nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)thin_sel(ks, p);
+      }
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < kThinT; ++x)
+    if (x < r.n) thin_insert(r, r.cj[x]);
+#pragma unroll
+  for (int x = 0; x < kThinO; ++x) {
+    r.oj[x] = -1;
+    if (x < r.no) {
+      r.oj[x] = g.Cin.col_idx[r.o0 + x];
+      thin_insert(r, r.oj[x]);
+    }
+  }
+  return true;
+}
+
+// Count pass of the thin rows; every other row goes to the list g.wide.
+__global__ __launch_bounds__(256) void k_sym_count_thin(SymArgs g) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.A.nbrows) return;
+  ThinRow r;
+  if (!thin_load(g, i, r)) {
+    g.wide[atomicAdd(g.n_wide, 1)] = i;
+    return;
+  }
+  int64_t sumn = 0;
+#pragma unroll
+  for (int x = 0; x < kThinC; ++x)
+    if (x < r.nc) sumn += g.c_col_sizes[r.col[x]];
+  const int64_t m = g.c_row_sizes[i];
+  g.row_nc[i] = r.nc;
+  g.row_np[i] = r.n;
+  g.row_nv[i] = m * sumn;
+  g.row_ncand[i] = r.T;
+  g.row_nf[i] = m * (int64_t)r.nf;
+}
+
+// Fill pass of the thin rows.
+__global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
+  if (g.totals[kTotAbort]) return;
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.A.nbrows) return;
+  ThinRow r;
+  if (!thin_load(g, i, r)) return;
+  const int32_t crow = g.c_row_ptr[i];
+  const int64_t prow = g.row_pstart[i], vrow = g.row_vstart[i];
+  const int64_t m = g.c_row_sizes[i];
+  int64_t pc = 0, vc = 0;
+#pragma unroll
+  for (int x = 0; x < kThinC; ++x) {
+    if (x < r.nc) {
+      const int32_t j = r.col[x];
+      int32_t o = -1;
+#pragma unroll
+      for (int y = 0; y < kThinO; ++y)
+        if (y < r.no && r.oj[y] == j) o = r.o0 + y;
+      g.c_col_idx[crow + x] = j;
+      g.c_old_idx[crow + x] = o;
+      g.prod_ptr[crow + x] = prow + pc;
+      g.c_blk_off[crow + x] = vrow + m * vc;
+#pragma unroll
+      for (int y = 0; y < kThinT; ++y) {
+        if (y < r.n && r.cj[y] == j) {
+          g.prod_a[prow + pc] = r.a0 + r.cp[y];
+          g.prod_b[prow + pc] = r.cq[y];
+          ++pc;
+        }
+      }
+      vc += g.c_col_sizes[j];
+    }
+  }
+}
+
 constexpr int kCountSmallRowA = 256;
 
 // Small form (13 KB of LDS, eight workgroups per CU): rows of at most 256 A blocks.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
   __shared__ CountShared<kCountSmallRowA> sh;
-  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+  const int32_t nw = *g.n_wide;
+  for (int32_t x = blockIdx.x; x < nw; x += gridDim.x) {
+    const int32_t i = g.wide[x];
     if (g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA) continue;  // uniform
     count_row<kCountSmallRowA>(g, i, sh);
   }
@@ -293,12 +470,14 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
   __shared__ int32_t nrows;
   const int tid = threadIdx.x;
   const int64_t G = gridDim.x;
-  for (int64_t i0 = blockIdx.x; i0 < g.A.nbrows; i0 += G * kSymThreads) {
+  const int32_t nw = *g.n_wide;
+  for (int64_t x0 = blockIdx.x; x0 < nw; x0 += G * kSymThreads) {
     if (tid == 0) nrows = 0;
     __syncthreads();
-    const int64_t i = i0 + G * tid;
-    if (i < g.A.nbrows && g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA)
-      rows[atomicAdd(&nrows, 1)] = (int32_t)i;
+    const int64_t x = x0 + G * tid;
+    const int32_t i = x < nw ? g.wide[x] : 0;
+    if (x < nw && g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA)
+      rows[atomicAdd(&nrows, 1)] = i;
     __syncthreads();
     const int32_t n = nrows;
     for (int32_t x = 0; x < n; ++x) count_row<kMaxRowA>(g, rows[x], sh);
@@ -616,7 +795,9 @@ template <class Cap, class Below>
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill_form(SymArgs g) {
   __shared__ FillShared<Cap> sh;
   if (g.totals[kTotAbort]) return;
-  for (int32_t i = blockIdx.x; i < g.A.nbrows; i += gridDim.x) {
+  const int32_t nw = *g.n_wide;
+  for (int32_t x = blockIdx.x; x < nw; x += gridDim.x) {
+    const int32_t i = g.wide[x];
     // uniform: every thread reads the same sizes
     if (!fill_fits<Cap>(g, i) || fill_fits<Below>(g, i)) continue;
     fill_row<Cap>(g, i, sh);
@@ -634,11 +815,13 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
   if (g.totals[kTotAbort]) return;
   const int tid = threadIdx.x;
   const int64_t G = gridDim.x;
-  for (int64_t i0 = blockIdx.x; i0 < g.A.nbrows; i0 += G * kSymThreads) {
+  const int32_t nw = *g.n_wide;
+  for (int64_t x0 = blockIdx.x; x0 < nw; x0 += G * kSymThreads) {
     if (tid == 0) nrows = 0;
     __syncthreads();
-    const int64_t i = i0 + G * tid;
-    if (i < g.A.nbrows && !fill_fits_small(g, (int32_t)i)) rows[atomicAdd(&nrows, 1)] = (int32_t)i;
+    const int64_t x = x0 + G * tid;
+    const int32_t i = x < nw ? g.wide[x] : 0;
+    if (x < nw && !fill_fits_small(g, i)) rows[atomicAdd(&nrows, 1)] = i;
     __syncthreads();
     const int32_t n = nrows;
     for (int32_t x = 0; x < n; ++x) {
@@ -650,9 +833,12 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
 
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sym_count_thin, dim3((a.A.nbrows + 255) / 256), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
   hipLaunchKernelGGL(k_sym_count_small, dim3(grid), dim3(kSymThreads), 0, s, a);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sym_count_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
@@ -660,9 +846,12 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
 
 hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sym_fill_thin, dim3((a.A.nbrows + 255) / 256), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
   hipLaunchKernelGGL((k_sym_fill_form<FillTiny, FillNone>), dim3(grid), dim3(kSymThreads), 0, s, a);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_sym_fill_form<FillSmall, FillTiny>), dim3(grid), dim3(kSymThreads), 0, s, a);
   e = hipGetLastError();
