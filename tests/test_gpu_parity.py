@@ -406,3 +406,41 @@ def test_fill_both_forms(case):
     large = ~tiny & ~small
     assert tiny.any() and (small.any() if case == "medium_rows" else large.any())
     check(ref, gpu_multiply(A, B, None, 1.0, 0.0, 0.0), exact=True)
+
+
+@pytest.mark.parametrize("beta,filt", [(0.0, False), (1.0, True)])
+def test_thin_and_wide_rows(beta, filt):
+    """Rows taken by the one-thread path (empty rows, one A block with short B
+    rows, few C_in blocks) mixed with rows the workgroup forms take, in one
+    multiply: pattern and stack exact, values within tolerance; the same in
+    reserved (device-sized) mode."""
+    rs, ks, cs = [5, 13, 23, 6] * 6, [13, 5, 7] * 8, [6, 23, 5] * 8
+    rng = np.random.default_rng(4242)
+    nr, nk, nc = len(rs), len(ks), len(cs)
+    mask_a = np.zeros((nr, nk), dtype=bool)
+    for i in range(nr):
+        if i % 3 == 0:
+            mask_a[i] = rng.random(nk) < 0.8       # wide row
+        elif i % 3 == 1:
+            mask_a[i, rng.integers(nk)] = True     # one A block
+    mask_b = rng.random((nk, nc)) < 0.15
+    mask_c = rng.random((nr, nc)) < 0.1
+    A = W.with_pattern(rs, ks, *W.pattern_from_mask(mask_a))
+    A.values = W.values_uniform(21, A.block_elems())
+    B = W.with_pattern(ks, cs, *W.pattern_from_mask(mask_b))
+    B.values = W.values_uniform(22, B.block_elems())
+    Co = W.with_pattern(rs, cs, *W.pattern_from_mask(mask_c))
+    Co.values = W.values_uniform(23, Co.block_elems())
+    eps = _eps_median(A, B) if filt else 0.0
+    ref = oracle.multiply(0.7, A, B, beta, Co if beta else None, eps)
+    check(ref, gpu_multiply(A, B, Co if beta else None, 0.7, beta, eps))
+    dA, dB, dCo = (bsmm.Matrix.from_csr(x) for x in (A, B, Co))
+    dC = bsmm.Matrix.empty(rs, cs)
+    bsmm.bsmm_reserve(dC.handle, nr * nc, int(np.sum(rs)) * int(np.sum(cs)), nr * nk * nc)
+    bsmm.multiply(0.7, dA, dB, beta, dCo if beta else None, dC, eps)
+    rp, ci, v = dC.to_host()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx)
+    assert np.array_equal(dC.stack(), ref.stack.reshape(-1, 3))
+    assert rel_err(v, ref.values) <= REL_TOL
+    for m in (dA, dB, dCo, dC):
+        m.close()
