@@ -449,7 +449,8 @@ __global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
 
 constexpr int kCountSmallRowA = 256;
 
-// Small form (13 KB of LDS, eight workgroups per CU): rows of at most 256 A blocks.
+// Small form (13 KB of LDS, eight workgroups per CU): the listed (not thin)
+// rows of at most 256 A blocks, one workgroup per row.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
   __shared__ CountShared<kCountSmallRowA> sh;
   const int32_t nw = *g.n_wide;
@@ -461,9 +462,9 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
 }
 
 // Large form: the longer rows (and rows beyond the limits, which it reports).
-// Workgroup w of G owns rows w, w+G, w+2G, ...; it looks at 256 of them at a
-// time, one per thread, and counts the long ones in turn, so long rows spread
-// over the whole grid while short ones cost one load each.
+// Workgroup w of G owns list entries w, w+G, w+2G, ...; it looks at 256 of
+// them at a time, one per thread, and counts the long rows in turn, so long
+// rows spread over the whole grid while short ones cost one load each.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
   __shared__ CountShared<kMaxRowA> sh;
   __shared__ int32_t rows[kSymThreads];
@@ -788,9 +789,9 @@ __device__ __forceinline__ bool fill_fits(const SymArgs& g, int32_t i) {
 
 __device__ __forceinline__ bool fill_fits_small(const SymArgs& g, int32_t i) { return fill_fits<FillSmall>(g, i); }
 
-// Small forms, one workgroup per row: form Cap takes the rows that fit it but
-// not the next smaller form Below (tiny: 21 KB of LDS, seven workgroups per
-// CU; small: 34 KB, four).
+// Small forms, one workgroup per row: of the listed (not thin) rows, form Cap
+// takes the ones that fit it but not the next smaller form Below (tiny: 21 KB
+// of LDS, seven workgroups per CU; small: 34 KB, four).
 template <class Cap, class Below>
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill_form(SymArgs g) {
   __shared__ FillShared<Cap> sh;
@@ -806,8 +807,8 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_form(SymArgs g) {
 }
 
 // Large form: the remaining rows, found as in the count pass (workgroup w of
-// G looks at rows w, w+G, ... 256 at a time and fills the ones the small
-// form leaves).
+// G looks at list entries w, w+G, ... 256 at a time and fills the rows the
+// small forms leave).
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
   __shared__ FillShared<FillLarge> sh;
   __shared__ int32_t rows[kSymThreads];
