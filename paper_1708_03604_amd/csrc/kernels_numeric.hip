@@ -486,6 +486,252 @@ __global__ __launch_bounds__(256, 2) void k_numeric_tile24(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Square blocks of edge S in [17, 24] on the FP64 matrix cores
+// (v_mfma_f64_4x4x4_4b: four independent 4x4x4 products per instruction, which
+// pad a 23-edge only to 24).  Same schedule as k_numeric_tile24 (one wave per
+// C block at a time, products as one stream per wave, two LDS stages); only
+// the block product and the block finish differ.
+//
+// Instruction layout (measured on the device): lane 16k + 4b + i holds
+// A_b[i][k] and B_b[k][i'] with i' = i, and the result lane 16i + 4b + j holds
+// D_b[i][j].  The 24x24 C block is a 3x3 grid of 8x8 super-tiles, each the
+// 2x2 tiles b = 2*bi + bj of one instruction, so a lane keeps one FP64
+// accumulator per super-tile (9 in all).  The inner index runs in pairs: the
+// two instructions of K step kp use t = 8kp + 2k and t = 8kp + 2k + 1 in slot
+// k, so one 16-byte LDS read gives a lane both: A is staged as stored and B
+// transposed, both with row stride 26 doubles (16-byte aligned rows, and the
+// eight rows one read touches fall on distinct banks).  Pads (row/column 23,
+// inner index 23) stay zero.  54 instructions per product.
+// ---------------------------------------------------------------------------
+constexpr int kMfmaStride = 26;
+constexpr int kMfmaOperand = kTileEdge * kMfmaStride;
+
+template <int S>
+__global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
+    const double* __restrict__ Av, const double* __restrict__ Bv, const double* __restrict__ Ov,
+    const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
+    const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals, int use_old,
+    double alpha, double beta) {
+  static_assert(S >= 17 && S <= kTileEdge, "matrix-core kernel covers edges 17..24");
+  constexpr int NE = S * S;
+  constexpr int PER = (NE + 63) / 64;
+  constexpr int LAST = NE - 64 * (PER - 1);
+  // per wave: two stages, each A then B^T
+  __shared__ __align__(16) double lds[4][2][2 * kMfmaOperand];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int x = lane; x < 4 * kMfmaOperand; x += 64) (&lds[wv][0][0])[x] = 0.0;
+
+  // LDS offset (doubles, within a stage) of element e = lane + 64u of a
+  // product: A as stored, B transposed
+  int offA[PER], offB[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (u < PER - 1 || lane < LAST) ? lane + 64 * u : 0;
+    const int r = e / S, c = e - r * S;
+    offA[u] = r * kMfmaStride + c;
+    offB[u] = kMfmaOperand + c * kMfmaStride + r;
+  }
+  const bool tail = lane < LAST;
+  // fragment reads: slot k = lane >> 4, tile b = (lane >> 2) & 3, row/column
+  // i = lane & 3 of the tile; super-tile (I, J) and K step kp add constants
+  const int fk = lane >> 4, fb = (lane >> 2) & 3, fi = lane & 3;
+  const int afrag = (4 * (fb >> 1) + fi) * kMfmaStride + 2 * fk;
+  const int bfrag = kMfmaOperand + (4 * (fb & 1) + fi) * kMfmaStride + 2 * fk;
+
+  constexpr int kXcds = 8;
+  constexpr int kChunk = 2;
+  const int32_t xcd = blockIdx.x % kXcds;
+  const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;  // waves per XCD
+  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
+  const int32_t nnzc = live_nnzc(totals);
+  if (nnzc == 0) return;
+  const int64_t P = prod_ptr[nnzc];
+  const int32_t X0 = lower_bound_c(prod_ptr, nnzc, P * xcd / kXcds);
+  const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_c(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
+
+  int32_t iq = wix;
+  int64_t ip = 0, ip_end = 0;
+  if (X0 + (int64_t)iq * kChunk < X1) {
+    const int32_t c0 = X0 + iq * kChunk;
+    ip = prod_ptr[c0];
+    ip_end = prod_ptr[min(c0 + kChunk, X1)];
+  }
+  auto next_index = [&]() -> int64_t {
+    while (ip >= ip_end) {
+      iq += wpx;
+      if (X0 + (int64_t)iq * kChunk >= X1) return -1;
+      const int32_t c0 = X0 + iq * kChunk;
+      ip = prod_ptr[c0];
+      ip_end = prod_ptr[min(c0 + kChunk, X1)];
+    }
+    return ip++;
+  };
+  int32_t qa0 = -1, qb0 = -1, qa1 = -1, qb1 = -1;
+  {
+    const int64_t n0 = next_index();
+    if (n0 >= 0) {
+      qa0 = prod_a[n0];
+      qb0 = prod_b[n0];
+    }
+    const int64_t n1 = next_index();
+    if (n1 >= 0) {
+      qa1 = prod_a[n1];
+      qb1 = prod_b[n1];
+    }
+  }
+  double opa[PER], opb[PER];
+  auto fetch_next = [&]() {
+    if (qa0 >= 0) {
+      const double* Ab = Av + (int64_t)qa0 * NE + lane;
+      const double* Bb = Bv + (int64_t)qb0 * NE + lane;
+#pragma unroll
+      for (int u = 0; u < PER - 1; ++u) {
+        opa[u] = Ab[64 * u];
+        opb[u] = Bb[64 * u];
+      }
+      opa[PER - 1] = tail ? Ab[64 * (PER - 1)] : 0.0;
+      opb[PER - 1] = tail ? Bb[64 * (PER - 1)] : 0.0;
+    }
+    qa0 = qa1;
+    qb0 = qb1;
+    const int64_t n = next_index();
+    qa1 = n >= 0 ? prod_a[n] : -1;
+    qb1 = n >= 0 ? prod_b[n] : -1;
+  };
+  auto stage_write = [&](const int st) {
+    double* base = &lds[wv][st][0];
+#pragma unroll
+    for (int u = 0; u < PER - 1; ++u) {
+      base[offA[u]] = opa[u];
+      base[offB[u]] = opb[u];
+    }
+    if (tail) {
+      base[offA[PER - 1]] = opa[PER - 1];
+      base[offB[PER - 1]] = opb[PER - 1];
+    }
+  };
+
+  const bool any = qa0 >= 0;
+  if (any) {
+    fetch_next();
+    stage_write(0);
+    fetch_next();
+  }
+  double acc[3][3];
+  auto step = [&](auto stage) {
+    constexpr int st = decltype(stage)::value;
+    stage_write(st ^ 1);
+    fetch_next();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double* base = &lds[wv][st][0];
+#pragma unroll
+    for (int kp = 0; kp < 3; ++kp) {
+      double2 a[3], b[3];
+#pragma unroll
+      for (int I = 0; I < 3; ++I) a[I] = *reinterpret_cast<const double2*>(base + afrag + 8 * I * kMfmaStride + 8 * kp);
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b[J] = *reinterpret_cast<const double2*>(base + bfrag + 8 * J * kMfmaStride + 8 * kp);
+#pragma unroll
+      for (int I = 0; I < 3; ++I)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I].x, b[J].x, acc[I][J], 0, 0, 0);
+#pragma unroll
+      for (int I = 0; I < 3; ++I)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I].y, b[J].y, acc[I][J], 0, 0, 0);
+    }
+  };
+
+  int32_t cq = wix;
+  int32_t c = 0, c1 = 0;
+  int64_t p = 0, pe = 0;
+  if (X0 + (int64_t)cq * kChunk >= X1) return;
+  c = X0 + cq * kChunk;
+  c1 = min(c + kChunk, X1);
+  p = prod_ptr[c];
+  pe = prod_ptr[c + 1];
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) acc[I][J] = 0.0;
+
+  // this lane's result element of super-tile (I, J): row 8I + orow, column 8J + ocol
+  const int orow = 4 * (fb >> 1) + fk, ocol = 4 * (fb & 1) + fi;
+  // Finish every C block that ends at p: apply alpha, park the block
+  // row-major in the free LDS stage, then add beta*C_in and store it with
+  // contiguous accesses.  Returns false when the wave has no products left.
+  auto advance = [&](auto freestage) -> bool {
+    constexpr int fs = decltype(freestage)::value;
+    double* const tile = &lds[wv][fs][0];
+    while (p == pe) {
+#pragma unroll
+      for (int I = 0; I < 3; ++I)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const int R = 8 * I + orow, Cc = 8 * J + ocol;
+          if (R < S && Cc < S) tile[R * S + Cc] = alpha * acc[I][J];
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int32_t o = use_old ? c_old_idx[c] : -1;
+      double* out = Cv + (int64_t)c * NE + lane;
+      const double* tl = tile + lane;
+      if (o >= 0) {
+        const double* ov = Ov + (int64_t)o * NE + lane;
+        double ol[PER];
+#pragma unroll
+        for (int u = 0; u < PER - 1; ++u) ol[u] = ov[64 * u];
+        ol[PER - 1] = tail ? ov[64 * (PER - 1)] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u] + beta * ol[u];
+        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)] + beta * ol[PER - 1];
+      } else {
+#pragma unroll
+        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u];
+        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)];
+      }
+      // the parked block overwrote some inner-index pads of the stage's A
+      // operand (positions r*26 + t, t >= S, below S*S): restore their zeros
+      // once every lane has read the parked block
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < kTileEdge) {
+#pragma unroll
+        for (int t = S; t < kTileEdge; ++t)
+          if (lane * kMfmaStride + t < NE) tile[lane * kMfmaStride + t] = 0.0;
+      }
+#pragma unroll
+      for (int I = 0; I < 3; ++I)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) acc[I][J] = 0.0;
+      ++c;
+      if (c == c1) {
+        cq += wpx;
+        if (X0 + (int64_t)cq * kChunk >= X1) return false;
+        c = X0 + cq * kChunk;
+        c1 = min(c + kChunk, X1);
+        p = prod_ptr[c];
+      }
+      pe = prod_ptr[c + 1];
+    }
+    return true;
+  };
+
+  for (;;) {
+    if (p == pe && !advance(std::integral_constant<int, 1>())) break;
+    step(std::integral_constant<int, 0>());
+    ++p;
+    if (p == pe && !advance(std::integral_constant<int, 0>())) break;
+    step(std::integral_constant<int, 1>());
+    ++p;
+  }
+}
+
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
   (void)work;
@@ -494,7 +740,7 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int32_t blocks = cus * 2;   // two workgroups of 4 waves per CU, a multiple of 8 (XCDs)
     blocks = ((blocks + 7) / 8) * 8;
-    hipLaunchKernelGGL(k_numeric_tile24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
+    hipLaunchKernelGGL(k_numeric_mfma24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
                        a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
                        a.c_values, a.totals, a.use_old, a.alpha, a.beta);
     return hipGetLastError();
