@@ -119,7 +119,12 @@ bsmm_status bsmm_destroy(bsmm_mat m);
  *   - alpha, beta and filter_eps must be finite (BSMM_E_ARG).
  *   - Synchronises `stream` once, after the symbolic phase, to size C_out,
  *     unless C_out is reserved (bsmm_reserve): then it never synchronises.
- * On error C_out is left as it was.
+ * Errors: a call rejected by its checks (arguments, shapes, aliasing, the
+ * symbolic pass limits, capacity, an unsupported precision/size pair) leaves
+ * C_out as it was, values, pattern and product stack included.  If device
+ * allocation (BSMM_E_NOMEM) or a HIP call (BSMM_E_HIP) fails after C_out began
+ * to be rewritten, C_out is left a valid empty matrix (no blocks, no product
+ * stack) and the message says so.
  */
 bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in,
                           bsmm_mat C_out, double filter_eps, int prec, void* stream);

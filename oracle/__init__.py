@@ -33,11 +33,34 @@ class OracleError(RuntimeError):
         self.code = code
 
 
+FLAGS = ["-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared"]
+
+
 def build():
     """Compile oracle.c into liboracle.so (plain gcc, OpenMP over block rows)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-o", _LIB_PATH, _SRC, "-lm"]
+    cmd = ["gcc"] + FLAGS + ["-o", _LIB_PATH, _SRC, "-lm"]
     subprocess.check_call(cmd)
+
+
+def use_native_build(directory):
+    """Compile oracle.c for the CPU this process runs on (adds -march=native;
+    still no FP contraction, so the results are the same bits) into
+    `directory` and use that library from now on.  Returns the compile line."""
+    global _lib
+    path = os.path.join(directory, "liboracle_native.so")
+    cmd = ["gcc"] + FLAGS + ["-march=native", "-o", path, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    _lib = None
+    _load(path)
+    return " ".join(cmd[:len(FLAGS) + 2])
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's row loop (the runtime it is linked with)."""
+    import ctypes.util
+    gomp = ctypes.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
 
 
 class _Mat(ctypes.Structure):
@@ -56,15 +79,17 @@ class _Mat(ctypes.Structure):
 _lib = None
 
 
-def _load():
+def _load(path=None):
     global _lib
     if _lib is not None:
         return _lib
-    stale = (not os.path.exists(_LIB_PATH)
-             or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC))
-    if stale:
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    if path is None:
+        path = _LIB_PATH
+        stale = (not os.path.exists(_LIB_PATH)
+                 or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC))
+        if stale:
+            build()
+    lib = ctypes.CDLL(path)
     P = ctypes.POINTER(_Mat)
     vp, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
     lib.oracle_check.argtypes = [P]

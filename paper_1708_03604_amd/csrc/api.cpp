@@ -34,6 +34,13 @@ bsmm_status fail(bsmm_status st, const std::string& msg) {
     if (e_ != hipSuccess) return fail(BSMM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// HIP_TRY for the part of a multiply that already rewrites the result matrix C.
+#define HIP_W(expr)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return empty_result(C, s, BSMM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
 // Growable device buffer.
 template <typename T>
 struct DBuf {
@@ -242,6 +249,25 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
   m->stats.nvals = t[kTotNvals];
   m->stats.useful_flops = 2.0 * (double)t[kTotFlopHalf];
   return BSMM_OK;
+}
+
+// A multiply that failed after it began to rewrite C (device allocation or a
+// HIP call): leave C a valid empty matrix without a product stack, so that no
+// later call reads half-written storage, and report `code`.
+bsmm_status empty_result(bsmm_matrix* C, hipStream_t s, bsmm_status code, const std::string& msg) {
+  C->nnzb = 0;
+  C->nvals = 0;
+  C->nprod = 0;
+  C->has_stack = false;
+  C->stats = bsmm_mult_stats{};
+  C->stats.variant = -1;
+  const int64_t zero[4] = {0, 0, 0, 0};
+  if (ensure_storage(C->cur, C->nbrows, 0, 0) == hipSuccess &&
+      hipMemsetAsync(C->cur.row_ptr.p, 0, sizeof(int32_t) * (C->nbrows + 1), s) == hipSuccess &&
+      hipMemsetAsync(C->cur.blk_off.p, 0, sizeof(int64_t), s) == hipSuccess &&
+      hipMemcpyAsync(C->dsz.p, zero, 3 * sizeof(int64_t), hipMemcpyHostToDevice, s) == hipSuccess)
+    (void)hipStreamSynchronize(s);
+  return fail(code, msg + " (the result matrix was left empty)");
 }
 
 // Tuning table of the small-block path: tuning key -> pipeline variant.
@@ -535,6 +561,9 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   const bool use_old = beta != 0.0 && C_in != nullptr;
   if (use_old && (!same_sizes(C_in->row_sizes, A->row_sizes) || !same_sizes(C_in->col_sizes, B->col_sizes)))
     return fail(BSMM_E_SHAPE, "C_in block sizes must be A's row sizes and B's column sizes");
+  const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
+  const bool split = prec == BSMM_SPLIT_BF16X3;
+  if (split && uniform != 23) return fail(BSMM_E_UNSUPPORTED, "split precision is built for uniform 23x23 blocks");
   const bool use_eps = filter_eps > 0.0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int32_t nbrows = A->nbrows;
@@ -644,6 +673,10 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     nvals_bound = nvals;
   }
 
+  // Every check that can reject the call has run: from here on C's storage
+  // and stack are rewritten.  A resource failure past this point leaves C a
+  // valid empty matrix without a stack (empty_result).
+  C->has_stack = false;
   // output storage: in place -> write the spare storage and swap afterwards
   const bool in_place = use_old && C_in == C;
   Storage& out = in_place ? C->spare : C->cur;
@@ -652,15 +685,12 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       C->prod_a.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
       C->prod_b.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
       C->old_idx.ensure(std::max<int64_t>(nnzc_bound, 1)) != hipSuccess)
-    return fail(BSMM_E_NOMEM, "device allocation for the result failed");
-  const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
-  const bool split = prec == BSMM_SPLIT_BF16X3;
+    return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the result failed");
   const bool small = !split && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
   if (split) {
-    if (uniform != 23) return fail(BSMM_E_UNSUPPORTED, "split precision is built for uniform 23x23 blocks");
     if (C->split_a.ensure(split_elems(std::max<int64_t>(blocks_bound(A), 1))) != hipSuccess ||
         C->split_b.ensure(split_elems(std::max<int64_t>(blocks_bound(B), 1))) != hipSuccess)
-      return fail(BSMM_E_NOMEM, "device allocation for the split operands failed");
+      return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the split operands failed");
   }
   if (small) {
     const int64_t ncl = class_list_tmp_elems(nnzc_bound), nce = class_entries(nnzc_bound);
@@ -671,13 +701,13 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
         C->class_start.ensure(5) != hipSuccess ||
         C->scan_tmp.ensure(std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(nce)}) + 2) !=
             hipSuccess)
-      return fail(BSMM_E_NOMEM, "device allocation for the block classes failed");
+      return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the block classes failed");
   }
   // a reallocation above may have freed C_in's storage only if C_in == C and
   // `out` is cur; that case is excluded by writing the spare.
   if (use_old) g.Cin = view(C_in);
   mark(C, ev, 3, s);
-  HIP_TRY(launch_finish_rows(nbrows, C->pre[0].p, C->pre[1].p, C->pre[2].p, out.row_ptr.p, C->prod_ptr.p,
+  HIP_W(launch_finish_rows(nbrows, C->pre[0].p, C->pre[1].p, C->pre[2].p, out.row_ptr.p, C->prod_ptr.p,
                              out.blk_off.p, C->totals.p, s));
   g.c_row_ptr = out.row_ptr.p;
   g.row_pstart = C->pre[1].p;
@@ -688,7 +718,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.c_old_idx = C->old_idx.p;
   g.prod_a = C->prod_a.p;
   g.prod_b = C->prod_b.p;
-  HIP_TRY(launch_sym_fill(g, s));
+  HIP_W(launch_sym_fill(g, s));
   mark(C, ev, 4, s);
 
   NumArgs na{};
@@ -711,22 +741,22 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.c_values = out.values.p;
   int32_t variant = -1;
   if (split) {
-    HIP_TRY(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
-    HIP_TRY(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
-    HIP_TRY(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
+    HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
+    HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
+    HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
   } else if (small) {
-    HIP_TRY(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
+    HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
     variant = tuned_variant(tune_key(A, B));
     if (std::max(A->max_edge, B->max_edge) > small_variant_max_edge(variant)) variant = kSmallDefault;
-    HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, variant,
+    HIP_W(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, variant,
                                  kSmallAllClasses, s));
     C->small_args = na;
   } else {
-    HIP_TRY(launch_numeric(na, uniform, C->work.p, s));
+    HIP_W(launch_numeric(na, uniform, C->work.p, s));
   }
   mark(C, ev, 5, s);
-  HIP_TRY(launch_finish_multiply(C->totals.p, out.values.p, C->dsz.p, s));
+  HIP_W(launch_finish_multiply(C->totals.p, out.values.p, C->dsz.p, s));
   mark(C, ev, 6, s);
 
   if (in_place) std::swap(C->cur, C->spare);
@@ -743,7 +773,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   C->stats.nvals = nvals;
   C->stats.useful_flops = 2.0 * (double)nflop_half;
   if (C->norm_self.ensure(std::max<int64_t>(nnzc, 1)) != hipSuccess)
-    return fail(BSMM_E_NOMEM, "scratch allocation failed");
+    return empty_result(C, s, BSMM_E_NOMEM, "scratch allocation failed");
   return BSMM_OK;
 }
 

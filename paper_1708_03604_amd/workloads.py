@@ -177,6 +177,46 @@ def random_matrix(seed, row_sizes, col_sizes, density, kind="uniform", lo=-4, hi
     return M
 
 
+def three_term_values(rng, n):
+    """Values x = p + q 2^-9 + r 2^-18 with |p|, |q| in 5..7 and |r| in 1..7
+    (random signs), returned as (x, [p, q 2^-9, r 2^-18]).  x is exact in FP64
+    (21 significant bits), and its BF16 split by repeated rounding to nearest
+    is exactly the three parts (each part stays inside one binade whose BF16
+    rounding error bound exceeds the parts below it)."""
+    def part(lo, hi):
+        return rng.integers(lo, hi + 1, size=n) * rng.choice([-1.0, 1.0], size=n)
+    parts = [part(5, 7), part(5, 7) * 2.0 ** -9, part(1, 7) * 2.0 ** -18]
+    return parts[0] + parts[1] + parts[2], parts
+
+
+def three_term_pair(seed, sizes, density=0.5):
+    """A and B on random square block patterns with three-term values (see
+    three_term_values); every A block has one nonzero per row (at a random
+    column), B blocks are full.  Returns (A, B, A_parts, B_parts), the parts
+    being three value arrays in A's (B's) layout that sum to its values."""
+    rng = np.random.default_rng(seed)
+    sizes = np.asarray(sizes, dtype=np.int32)
+    out = []
+    for which in range(2):
+        mask = rng.random((len(sizes), len(sizes))) < density
+        rp, ci = pattern_from_mask(mask)
+        M = with_pattern(sizes, sizes, rp, ci)
+        vals, parts = three_term_values(rng, M.nvals)
+        if which == 0:
+            keep = np.zeros(M.nvals, dtype=bool)
+            off = M.block_offsets()
+            rows = M.block_rows()
+            for b in range(M.nnzb):
+                m, n = sizes[rows[b]], sizes[M.col_idx[b]]
+                cols = rng.integers(0, n, size=m)
+                keep[off[b] + np.arange(m) * n + cols] = True
+            vals = np.where(keep, vals, 0.0)
+            parts = [np.where(keep, x, 0.0) for x in parts]
+        M.values = vals
+        out.append((M, parts))
+    return out[0][0], out[1][0], out[0][1], out[1][1]
+
+
 # ------------------------------------------------------- paper-shaped configs
 
 def grid23(seed=1000, nb=64, p=0.3, bs=23):
