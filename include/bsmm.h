@@ -140,6 +140,25 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
 bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): bsmm_filter with the same
+ * result bits, that allocates nothing.  Its temporaries (block norms, keep
+ * flags, the two scans) live in one fixed scratch array of the library, 6 MiB
+ * on every GPU it runs on, held until the process ends; the compacted matrix
+ * goes to the matrix's second storage, which must already hold the matrix's
+ * size (bsmm_reserve provides it; so does one earlier bsmm_filter or in-place
+ * multiply of at least this size).
+ *   - At most 131072 blocks (the reserved block capacity for a reserved
+ *     matrix), else BSMM_E_CAPACITY; BSMM_E_CAPACITY too if the second
+ *     storage is smaller than the matrix.  Nothing is changed on error.
+ *   - Reads the new size back like bsmm_filter (synchronises `stream`) except
+ *     for a reserved matrix.
+ *   - Every call on one GPU uses that GPU's one scratch array: calls that
+ *     overlap in time on one GPU (other streams, other threads) race.
+ */
+bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, void* stream);
+
+/*
  * Frobenius norm of every stored block, in CSR order, into out[nnzb]
  * (device memory owned by the caller; for a device-sized matrix it must hold
  * the reserved block capacity).  The sum of squares runs in a fixed

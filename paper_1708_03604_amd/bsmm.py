@@ -51,6 +51,7 @@ SIGNATURES = {
     "bsmm_destroy": ([_vp], _int),
     "bsmm_multiply": ([_dbl, _vp, _vp, _dbl, _vp, _vp, _dbl, _int, _vp], _int),
     "bsmm_filter": ([_vp, _dbl, _vp], _int),
+    "bsmm_filter_noalloc": ([_vp, _dbl, _vp], _int),
     "bsmm_norms": ([_vp, _vp, _vp], _int),
     "bsmm_info": ([_vp, _vp, _vp, _vp, _vp], _int),
     "bsmm_export": ([_vp, _vp, _vp, _vp, _int, _vp], _int),
@@ -157,6 +158,10 @@ def bsmm_multiply(alpha, A, B, beta, C_in, C_out, filter_eps, prec=BSMM_FP64, st
 
 def bsmm_filter(M, eps, stream=None):
     _check("bsmm_filter", lib().bsmm_filter(M, float(eps), _stream(stream)))
+
+
+def bsmm_filter_noalloc(M, eps, stream=None):
+    _check("bsmm_filter_noalloc", lib().bsmm_filter_noalloc(M, float(eps), _stream(stream)))
 
 
 def bsmm_norms(M, out, stream=None):

@@ -807,6 +807,99 @@ bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream) {
   return BSMM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of bsmm_filter_noalloc: file-scope device memory (one copy on every
+// GPU the library runs on, held until the process ends).  Host code never
+// passes `scratch` itself to a kernel: it takes the device address from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int64_t kNoAllocMaxBlocks = 131072;
+constexpr size_t kNoAllocScratchBytes = 6u << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (nullptr on failure,
+// with the reason in g_err).
+void* noalloc_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    g_err = "no current HIP device (or device index beyond " + std::to_string(kMaxDevices) + ")";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, void* stream) {
+  g_err.clear();
+  if (!m) return fail(BSMM_E_ARG, "NULL handle");
+  if (!is_finite(eps)) return fail(BSMM_E_ARG, "eps must be finite");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool reserved = m->cap_nnzb > 0;
+  const int64_t bound = reserved ? m->cap_nnzb : m->nnzb;
+  const int64_t vbound = reserved ? m->cap_nvals : m->nvals;
+  if (bound > kNoAllocMaxBlocks)
+    return fail(BSMM_E_CAPACITY, "bsmm_filter_noalloc handles at most " + std::to_string(kNoAllocMaxBlocks) +
+                                     " blocks (reserved capacity for a reserved matrix); this matrix has " +
+                                     std::to_string(bound));
+  // the result goes to the matrix's second storage, which must already exist
+  if (!m->spare.row_ptr.p || m->spare.row_ptr.cap < m->nbrows + 1 || m->spare.col_idx.cap < std::max<int64_t>(bound, 1) ||
+      m->spare.blk_off.cap < bound + 1 || m->spare.values.cap < vbound + kValueSlack)
+    return fail(BSMM_E_CAPACITY, "bsmm_filter_noalloc needs the matrix's second storage at its size: reserve the "
+                                 "matrix (bsmm_reserve) or filter it once with bsmm_filter first");
+  // scratch layout: norms[bound], keep[bound+1], vsz[bound+1], keep_pos[bound+1],
+  // voff[bound+1], scan temporaries; each part 256-byte aligned
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t nb = up(sizeof(double) * std::max<int64_t>(bound, 1));
+  const size_t ni = up(sizeof(int64_t) * (bound + 1));
+  const size_t nt = up(sizeof(int64_t) * (std::max(scan_tmp_elems(bound), scan_tmp_elems(m->nbrows)) + 2));
+  if (nb + 4 * ni + nt > kNoAllocScratchBytes)
+    return fail(BSMM_E_CAPACITY, "bsmm_filter_noalloc: the scan temporaries of " + std::to_string(m->nbrows) +
+                                     " block rows exceed the fixed scratch");
+  unsigned char* base = static_cast<unsigned char*>(noalloc_scratch());
+  if (!base) return fail(BSMM_E_HIP, g_err);
+  double* norms = reinterpret_cast<double*>(base);
+  int64_t* keep = reinterpret_cast<int64_t*>(base + nb);
+  int64_t* vsz = reinterpret_cast<int64_t*>(base + nb + ni);
+  int64_t* kpos = reinterpret_cast<int64_t*>(base + nb + 2 * ni);
+  int64_t* voff = reinterpret_cast<int64_t*>(base + nb + 3 * ni);
+  int64_t* tmp = reinterpret_cast<int64_t*>(base + nb + 4 * ni);
+  // every scratch entry the kernels read is written first by this call
+  // (flags past the live block count are written as zeros), so stale
+  // contents of an earlier call do not matter
+  HIP_TRY(launch_block_norms(m->cur.blk_off.p, m->cur.values.p, m->dsz.p, bound, max_block(m), norms, s));
+  HIP_TRY(launch_filter(m->cur.row_ptr.p, m->cur.col_idx.p, m->cur.blk_off.p, m->cur.values.p, m->nbrows, m->dsz.p,
+                        bound, norms, eps, keep, vsz, kpos, voff, tmp, m->spare.row_ptr.p, m->spare.col_idx.p,
+                        m->spare.blk_off.p, m->spare.values.p, s));
+  std::swap(m->cur, m->spare);
+  m->has_stack = false;  // block indices changed
+  if (reserved) return BSMM_OK;
+  int64_t sizes[2] = {0, 0};  // pageable host memory: a synchronous read-back, no allocation
+  HIP_TRY(hipMemcpyAsync(sizes, m->dsz.p, sizeof(sizes), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  m->nnzb = (int32_t)sizes[0];
+  m->nvals = sizes[1];
+  return BSMM_OK;
+}
+
 bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_t max_products, void* stream) {
   g_err.clear();
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
