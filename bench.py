@@ -157,7 +157,7 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
     return gm, rows
 
 
-PATH_NAMES = {0: "generic", 1: "tile23", 2: "small", 3: "split23"}
+PATH_NAMES = {0: "generic", 1: "tile23", 2: "small", 3: "split23", 4: "slice23"}
 
 
 def take_rows(M, rows):
@@ -281,17 +281,15 @@ def small_class_leg(w, dA, dB, dCin, dC, stream, reps=5):
             "the whole grid over that class's list), mean of the tuner's launches", "classes": classes}
 
 
-def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_ms):
-    """Same multiply with the operands split into three BF16 terms on matrix
-    cores; error against the FP64 result (which matches the oracle within
-    1e-12, see the parity tests)."""
+def _time_precision(w, dA, dB, dCin, stream, steps, warmup, prec):
+    """Time the multiply in precision `prec` into a fresh C; returns
+    (ms per step, numeric-phase ms, stats, values)."""
     from paper_1708_03604_amd import bsmm
     import torch
-    _, _, ref = dC.to_host()
     dS = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
 
     def step():
-        bsmm.multiply(w.alpha, dA, dB, w.beta, dCin, dS, w.eps, prec=bsmm.BSMM_SPLIT_BF16X3, stream=stream)
+        bsmm.multiply(w.alpha, dA, dB, w.beta, dCin, dS, w.eps, prec=prec, stream=stream)
 
     for _ in range(warmup):
         step()
@@ -307,9 +305,23 @@ def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_
     stats = bsmm.bsmm_stats(dS.handle)
     _, _, got = dS.to_host()
     dS.close()
+    return ms, phases["numeric"] / max(nrec, 1), stats, got
+
+
+def _error_record(got, ref):
     err = got - ref
-    rel = float(np.linalg.norm(err) / np.linalg.norm(ref))
-    numeric = phases["numeric"] / max(nrec, 1)
+    return {"rel_frobenius_vs_fp64": float(np.linalg.norm(err) / np.linalg.norm(ref)),
+            "max_abs_err": float(np.max(np.abs(err))),
+            "max_abs_err_over_max_abs_c": float(np.max(np.abs(err)) / np.max(np.abs(ref)))}
+
+
+def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_ms):
+    """Same multiply with the operands split into three BF16 terms on matrix
+    cores; error against the FP64 result (which matches the oracle within
+    1e-12, see the parity tests)."""
+    from paper_1708_03604_amd import bsmm
+    _, _, ref = dC.to_host()
+    ms, numeric, stats, got = _time_precision(w, dA, dB, dCin, stream, steps, warmup, bsmm.BSMM_SPLIT_BF16X3)
     # roofline of the split form: matrix-core peak over the six BF16 term
     # products, against the algorithmic FP64 bytes at the HBM peak
     flops = stats["useful_flops"]
@@ -323,15 +335,57 @@ def split_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_
             "traffic": None, "peak_note": f"min(2.5 PFLOP/s BF16 / 6 terms = {mfma_eq:.0f}, "
             f"{flops / ab:.1f} flop/B x 8 TB/s = {hbm_eq:.0f})",
             "kernel": "split pre-pass + split numeric kernel (numeric phase)"}
-    return {"value": round(stats["useful_flops"] / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "roofline": roof,
-            "ms_per_step": round(ms, 4), "numeric_ms": round(numeric, 4),
-            "speedup_vs_fp64": round(fp64_ms / ms, 3), "numeric_speedup_vs_fp64": round(fp64_numeric_ms / numeric, 3),
-            "rel_frobenius_vs_fp64": rel, "max_abs_err": float(np.max(np.abs(err))),
-            "max_abs_err_over_max_abs_c": float(np.max(np.abs(err)) / np.max(np.abs(ref))),
-            "stated_bound": "per element 2^-15 |alpha| (|A||B|)_ij + FP64 rounding (rigorous); the tests also "
-                            "assert relative Frobenius <= 1e-7 and max-abs <= 1e-6 max|C| (dropping any one of "
-                            "the six BF16 term products gives >= 2e-6)",
-            "note": "numeric_ms includes splitting A and B into BF16 terms"}
+    out = {"value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "roofline": roof,
+           "ms_per_step": round(ms, 4), "numeric_ms": round(numeric, 4),
+           "speedup_vs_fp64": round(fp64_ms / ms, 3), "numeric_speedup_vs_fp64": round(fp64_numeric_ms / numeric, 3)}
+    out.update(_error_record(got, ref))
+    out.update({"stated_bound": "per element 2^-15 |alpha| (|A||B|)_ij + FP64 rounding (rigorous); the tests "
+                                "also assert relative Frobenius <= 1e-7 and max-abs <= 1e-6 max|C| (dropping any "
+                                "one of the six BF16 term products gives >= 2e-6)",
+                "equal_accuracy": False,
+                "note": "numeric_ms includes splitting A and B into BF16 terms"})
+    return out
+
+
+# INT8 matrix-core work of one exact-slice 23x23 block product: 28 digit
+# products, each one 32x32x32 INT8 MFMA (the 23x23x23 product padded)
+SLICE_MFMA_OPS_PER_PRODUCT = 28 * 2 * 32 ** 3
+INT8_MFMA_PEAK_TOPS = 5000.0
+
+
+def slice_leg(w, dA, dB, dCin, dC, stream, steps, warmup, fp64_ms, fp64_numeric_ms):
+    """Same multiply in exact-slice precision (seven INT8 digits per value,
+    the 28 digit products of combined order <= 8 on INT8 matrix cores, exact
+    INT32 sums): FP64-level accuracy, timed next to FP64."""
+    from paper_1708_03604_amd import bsmm
+    _, _, ref = dC.to_host()
+    ms, numeric, stats, got = _time_precision(w, dA, dB, dCin, stream, steps, warmup, bsmm.BSMM_SLICE_INT8X7)
+    flops = stats["useful_flops"]
+    # matrix-core bound in FP64-equivalent flops: the INT8 peak times useful
+    # flops per executed INT8 op (2*23^3 per 28 padded 32x32x32 products)
+    useful_per_op = 2.0 * 23 ** 3 / SLICE_MFMA_OPS_PER_PRODUCT
+    mfma_eq = INT8_MFMA_PEAK_TOPS * useful_per_op
+    ab = algorithmic_bytes(w, stats["nvals"])
+    hbm_eq = flops / ab * HBM_PEAK_GBS / 1e3
+    peak = min(mfma_eq, hbm_eq)
+    achieved = flops / (numeric * 1e-3) / 1e12
+    int8_tops = stats["products"] * SLICE_MFMA_OPS_PER_PRODUCT / (numeric * 1e-3) / 1e12
+    roof = {"bound": "hbm" if hbm_eq < mfma_eq else "mfma", "achieved": round(achieved, 3),
+            "peak": round(peak, 2), "unit": "TFLOP/s (FP64-equivalent)", "frac": round(achieved / peak, 4),
+            "traffic": None, "peak_note": f"min(5.0 POP/s INT8 x {useful_per_op:.4f} useful flop per INT8 op = "
+            f"{mfma_eq:.1f}, {flops / ab:.1f} flop/B x 8 TB/s = {hbm_eq:.0f})",
+            "int8_tops_executed": round(int8_tops, 1),
+            "kernel": "slice pre-pass + slice numeric kernel (numeric phase)"}
+    out = {"value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "roofline": roof,
+           "ms_per_step": round(ms, 4), "numeric_ms": round(numeric, 4),
+           "speedup_vs_fp64": round(fp64_ms / ms, 3), "numeric_speedup_vs_fp64": round(fp64_numeric_ms / numeric, 3)}
+    out.update(_error_record(got, ref))
+    out.update({"stated_bound": "per element 2^-39 |alpha| n_ij MA(i,r) MB(j,q) + FP64 rounding (rigorous); the "
+                                "tests assert relative Frobenius <= 1e-13 and bit equality with the CPU model of "
+                                "the scheme",
+                "equal_accuracy": True,
+                "note": "numeric_ms includes the exponent and digit pre-passes over A and B"})
+    return out
 
 
 def chain_leg(nmol, steps=12, eps=1e-7, replays=3, prec=None):
@@ -522,6 +576,12 @@ def main():
         sp = out["split_bf16x3"]
         log(f"[bench] split: {sp['ms_per_step']} ms/step ({sp['speedup_vs_fp64']}x), rel Frobenius error "
             f"{sp['rel_frobenius_vs_fp64']:.2e}")
+        log("[bench] exact-slice precision (seven INT8 digits on matrix cores)")
+        out["slice_int8x7"] = slice_leg(w, dA, dB, dCin, dC, stream, args.steps, args.warmup, ms_per_step,
+                                        numeric_ms)
+        sl = out["slice_int8x7"]
+        log(f"[bench] slice: {sl['ms_per_step']} ms/step ({sl['speedup_vs_fp64']}x), rel Frobenius error "
+            f"{sl['rel_frobenius_vs_fp64']:.2e}")
     if args.workload == "water":
         log("[bench] per shape class timing of the small-block kernel")
         out["small_classes"] = small_class_leg(w, dA, dB, dCin, dC, stream)

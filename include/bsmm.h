@@ -52,12 +52,25 @@ typedef enum {
 typedef enum {
   BSMM_FP64 = 0,          /* FP64 products and accumulation */
   BSMM_SPLIT_F32X2 = 1,   /* two FP32 terms per value: not built (BSMM_E_UNSUPPORTED) */
-  BSMM_SPLIT_BF16X3 = 2   /* three BF16 terms per value, the six term products of combined
+  BSMM_SPLIT_BF16X3 = 2,  /* three BF16 terms per value, the six term products of combined
                              order <= 2 on BF16 matrix cores with FP32 accumulation, each
                              block product added in FP64; 23x23 blocks only
                              (BSMM_E_UNSUPPORTED otherwise).  Per C element the error is
                              below 2^-15 * |alpha| * sum_k |A(i,k)| |B(k,j)| plus FP64
                              rounding. */
+  BSMM_SLICE_INT8X7 = 3   /* exact slices (Ozaki-style splitting of the block products of
+                             Section 2): every value is scaled by a power of two per row of
+                             its block row (A) or per column of its block column (B) and cut
+                             into seven signed 7-bit digits; the digit products of combined
+                             order <= 8 run on INT8 matrix cores with exact INT32 sums over
+                             all products of a C block, combined in FP64 at its end.  23x23
+                             blocks only (BSMM_E_UNSUPPORTED otherwise); values must be
+                             finite.  Per element (r,q) of C(i,j) the error is below
+                             2^-39 * |alpha| * n_ij * MA(i,r) * MB(j,q) plus FP64 rounding of
+                             the alpha/beta update, with n_ij the performed block products,
+                             MA(i,r) the largest |A| in row r of block row i and MB(j,q) the
+                             largest |B| in column q of block column j.  Its digit buffers
+                             are allocated on first use, also for a reserved C_out. */
 } bsmm_prec;
 
 enum { BSMM_PTR_HOST = 0, BSMM_PTR_DEVICE = 1 };
@@ -67,7 +80,8 @@ enum {
   BSMM_PATH_GENERIC = 0, /* any other block sizes, FP64, in 32x32 sub-tiles and K chunks of 32 */
   BSMM_PATH_TILE23 = 1,  /* uniform 23x23 blocks, FP64 */
   BSMM_PATH_SMALL = 2,   /* every block edge <= 16, FP64, one launch over all shape classes */
-  BSMM_PATH_SPLIT23 = 3  /* uniform 23x23 blocks, BSMM_SPLIT_BF16X3 */
+  BSMM_PATH_SPLIT23 = 3, /* uniform 23x23 blocks, BSMM_SPLIT_BF16X3 */
+  BSMM_PATH_SLICE23 = 4  /* uniform 23x23 blocks, BSMM_SLICE_INT8X7 */
 };
 
 /* Number of compiled pipeline variants of the small-block path. */

@@ -21,12 +21,14 @@ STATUS_NAMES = {0: "BSMM_OK", 1: "BSMM_E_ARG", 2: "BSMM_E_SHAPE", 3: "BSMM_E_PAT
 BSMM_FP64 = 0
 BSMM_SPLIT_F32X2 = 1
 BSMM_SPLIT_BF16X3 = 2
+BSMM_SLICE_INT8X7 = 3
 BSMM_PTR_HOST = 0
 BSMM_PTR_DEVICE = 1
 BSMM_PATH_GENERIC = 0
 BSMM_PATH_TILE23 = 1
 BSMM_PATH_SMALL = 2
 BSMM_PATH_SPLIT23 = 3
+BSMM_PATH_SLICE23 = 4
 BSMM_SMALL_VARIANTS = 6
 
 

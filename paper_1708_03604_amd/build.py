@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbsmm.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "kernels_common.hip", "kernels_symbolic.hip", "kernels_numeric.hip", "kernels_small.hip", "kernels_split.hip"]
+SOURCES = ["api.cpp", "kernels_common.hip", "kernels_symbolic.hip", "kernels_numeric.hip", "kernels_small.hip", "kernels_split.hip", "kernels_slice.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",

@@ -123,6 +123,8 @@ struct bsmm_matrix {
   DBuf<int4> class_list;          // C blocks by padded shape class (small-block path), 2 per block
   DBuf<int4> prod_desc;           // per product operand offsets (small-block path)
   DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
+  DBuf<uint8_t> slice_a, slice_b;  // INT8 digits of the operands (exact-slice precision)
+  DBuf<int32_t> slice_ea, slice_eb, slice_rowof;  // their scale exponents; block rows of A's blocks
   DBuf<int64_t> class_cnt, class_pre, class_np, class_q;
   DBuf<int32_t> class_start;
   NumArgs small_args{};  // arguments of the last small-block launch (re-launched by the tuner)
@@ -414,6 +416,9 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->prod_desc.release();
   m->split_a.release();
   m->split_b.release();
+  m->slice_a.release();
+  m->slice_b.release();
+  for (auto* b : {&m->slice_ea, &m->slice_eb, &m->slice_rowof}) b->release();
   m->class_cnt.release();
   m->class_np.release();
   m->class_q.release();
@@ -548,7 +553,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   if (!A || !B || !C) return fail(BSMM_E_ARG, "NULL handle");
   if (!is_finite(alpha) || !is_finite(beta) || !is_finite(filter_eps))
     return fail(BSMM_E_ARG, "alpha, beta and filter_eps must be finite");
-  if (prec != BSMM_FP64 && prec != BSMM_SPLIT_F32X2 && prec != BSMM_SPLIT_BF16X3)
+  if (prec != BSMM_FP64 && prec != BSMM_SPLIT_F32X2 && prec != BSMM_SPLIT_BF16X3 && prec != BSMM_SLICE_INT8X7)
     return fail(BSMM_E_ARG, "unknown precision");
   if (prec == BSMM_SPLIT_F32X2)
     return fail(BSMM_E_UNSUPPORTED, "the two-term FP32 split is not built (FP32 matrix cores run at twice the FP64 "
@@ -564,6 +569,9 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   const int uniform = (A->uniform && A->uniform == B->uniform) ? A->uniform : 0;
   const bool split = prec == BSMM_SPLIT_BF16X3;
   if (split && uniform != 23) return fail(BSMM_E_UNSUPPORTED, "split precision is built for uniform 23x23 blocks");
+  const bool slice = prec == BSMM_SLICE_INT8X7;
+  if (slice && uniform != 23)
+    return fail(BSMM_E_UNSUPPORTED, "exact-slice precision is built for uniform 23x23 blocks");
   const bool use_eps = filter_eps > 0.0;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int32_t nbrows = A->nbrows;
@@ -686,11 +694,19 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       C->prod_b.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
       C->old_idx.ensure(std::max<int64_t>(nnzc_bound, 1)) != hipSuccess)
     return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the result failed");
-  const bool small = !split && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
+  const bool small = !split && !slice && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
   if (split) {
     if (C->split_a.ensure(split_elems(std::max<int64_t>(blocks_bound(A), 1))) != hipSuccess ||
         C->split_b.ensure(split_elems(std::max<int64_t>(blocks_bound(B), 1))) != hipSuccess)
       return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the split operands failed");
+  }
+  if (slice) {
+    const int64_t ba = std::max<int64_t>(blocks_bound(A), 1), bb = std::max<int64_t>(blocks_bound(B), 1);
+    if (C->slice_a.ensure(slice_bytes(ba)) != hipSuccess || C->slice_b.ensure(slice_bytes(bb)) != hipSuccess ||
+        C->slice_ea.ensure(23 * std::max<int64_t>(A->nbrows, 1)) != hipSuccess ||
+        C->slice_eb.ensure(23 * std::max<int64_t>(B->nbcols, 1)) != hipSuccess ||
+        C->slice_rowof.ensure(ba) != hipSuccess)
+      return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the slice operands failed");
   }
   if (small) {
     const int64_t ncl = class_list_tmp_elems(nnzc_bound), nce = class_entries(nnzc_bound);
@@ -744,6 +760,13 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
     HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
     HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
+  } else if (slice) {
+    HIP_W(launch_slice_int8x7(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, A->cur.row_ptr.p, A->nbrows, nullptr,
+                                A->nbrows, C->slice_rowof.p, C->slice_ea.p, C->slice_a.p, s));
+    HIP_W(launch_slice_int8x7(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, nullptr, 0, B->cur.col_idx.p, B->nbcols,
+                                nullptr, C->slice_eb.p, C->slice_b.p, s));
+    HIP_W(launch_numeric_slice23(na, out.row_ptr.p, nbrows, C->slice_a.p, C->slice_b.p, C->slice_ea.p,
+                                   C->slice_eb.p, s));
   } else if (small) {
     HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
@@ -761,7 +784,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
 
   if (in_place) std::swap(C->cur, C->spare);
   C->has_stack = true;
-  C->stats.path = split ? BSMM_PATH_SPLIT23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
+  C->stats.path = split ? BSMM_PATH_SPLIT23 : slice ? BSMM_PATH_SLICE23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
   C->stats.variant = variant;
   if (reserved) return BSMM_OK;
   C->nnzb = (int32_t)nnzc;

@@ -178,6 +178,18 @@ hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int6
                                uint16_t* out, hipStream_t s);
 hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, hipStream_t s);
 
+// Exact-slice precision (23x23 blocks): seven INT8 digits per value under a
+// power-of-two scale per row of each block row of A (transpose = 0, scale
+// groups = block rows, rowof: scratch of `bound` entries) or per column of
+// each block column of B (transpose = 1, groups = block columns);
+// slice_bytes(nblocks) bytes of digits, exps[ngroups*23] exponents.
+int64_t slice_bytes(int64_t nblocks);
+hipError_t launch_slice_int8x7(const double* values, const int64_t* d_nnzb, int64_t bound, int transpose,
+                               const int32_t* row_ptr, int32_t nbrows, const int32_t* col_idx, int32_t ngroups,
+                               int32_t* rowof, int32_t* exps, uint8_t* out, hipStream_t s);
+hipError_t launch_numeric_slice23(const NumArgs& a, const int32_t* c_row_ptr, int32_t nbrows, const uint8_t* As,
+                                  const uint8_t* Bs, const int32_t* ea, const int32_t* eb, hipStream_t s);
+
 // filter(M, eps) over the first dsz[0] blocks (bound >= dsz[0] sizes the
 // launches; keep/vsz/keep_pos/voff are scratch of bound (+1) entries).  The
 // new sizes replace dsz[0..1].

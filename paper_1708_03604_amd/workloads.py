@@ -217,6 +217,37 @@ def three_term_pair(seed, sizes, density=0.5):
     return out[0][0], out[1][0], out[0][1], out[1][1]
 
 
+def seven_digit_values(rng, n):
+    """Values x = sum_s d_s 2^-(6 + 7(s-1)), s = 1..7, with |d_1| in 33..63 and
+    d_2..d_7 in -63..63 (random signs and digits), returned as (x, digits),
+    digits an int array of shape (7, n).  x is exact in FP64 (at most 49
+    significant bits) and lies in [0.5, 1) in magnitude, so any row or column
+    of such values has the power-of-two scale 1, and rounding to nearest
+    recovers the digits one by one (every tail is below one half)."""
+    d = rng.integers(-63, 64, size=(7, n))
+    d[0] = rng.integers(33, 64, size=n) * rng.choice([-1, 1], size=n)
+    x = np.zeros(n)
+    for s in range(6, -1, -1):  # smallest first: every partial sum is exact
+        x = x + d[s] * 2.0 ** -(6 + 7 * s)
+    return x, d
+
+
+def seven_digit_pair(seed, sizes, density=0.5):
+    """A and B on random square block patterns, every value a seven-digit
+    value (see seven_digit_values).  Returns (A, B, A_digits, B_digits), the
+    digits as (7, nvals) arrays in A's (B's) value layout."""
+    rng = np.random.default_rng(seed)
+    sizes = np.asarray(sizes, dtype=np.int32)
+    out = []
+    for _ in range(2):
+        mask = rng.random((len(sizes), len(sizes))) < density
+        rp, ci = pattern_from_mask(mask)
+        M = with_pattern(sizes, sizes, rp, ci)
+        M.values, digits = seven_digit_values(rng, M.nvals)
+        out.append((M, digits))
+    return out[0][0], out[1][0], out[0][1], out[1][1]
+
+
 # ------------------------------------------------------- paper-shaped configs
 
 def grid23(seed=1000, nb=64, p=0.3, bs=23):
