@@ -959,12 +959,18 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
   }
   const int64_t ncl = class_list_tmp_elems(cb), nce = class_entries(cb);
   const int64_t tmp = std::max({scan_tmp_elems(nbrows), scan_tmp_elems(ncl), scan_tmp_elems(cb), scan_tmp_elems(nce)}) + 2;
+  // the small-block path's descriptors and class lists (16 bytes per
+  // product) only where that path can write this matrix: C's block edges are
+  // A's row and B's column edges, so an edge above kSmallEdge rules it out
+  const bool small_ok = m->max_edge <= kSmallEdge;
   bool ok = ensure_storage(m->spare, nbrows, cb, cv) == hipSuccess && m->prod_ptr.ensure(cb + 1) == hipSuccess &&
             m->prod_a.ensure(cp) == hipSuccess && m->prod_b.ensure(cp) == hipSuccess &&
-            m->old_idx.ensure(cb) == hipSuccess && m->prod_desc.ensure(cp) == hipSuccess &&
-            m->class_list.ensure(2 * cb) == hipSuccess && m->class_cnt.ensure(ncl) == hipSuccess &&
-            m->class_pre.ensure(ncl) == hipSuccess && m->class_start.ensure(5) == hipSuccess &&
-            m->class_np.ensure(nce) == hipSuccess && m->class_q.ensure(nce + 1) == hipSuccess &&
+            m->old_idx.ensure(cb) == hipSuccess &&
+            (!small_ok ||
+             (m->prod_desc.ensure(cp) == hipSuccess && m->class_list.ensure(2 * cb) == hipSuccess &&
+              m->class_cnt.ensure(ncl) == hipSuccess && m->class_pre.ensure(ncl) == hipSuccess &&
+              m->class_start.ensure(5) == hipSuccess && m->class_np.ensure(nce) == hipSuccess &&
+              m->class_q.ensure(nce + 1) == hipSuccess)) &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
             m->flags.ensure(2) == hipSuccess && m->work.ensure(1) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&

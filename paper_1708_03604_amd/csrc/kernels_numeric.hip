@@ -190,51 +190,10 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Square blocks of edge S in [13, 24] (the 23x23 molecule blocks): one wave
-// per C block at a time, the block padded to a 24x24 register tile.
-//
-// Work split: the product stack is one flat array ordered by C block, so each
-// wave takes a contiguous run of C blocks holding an equal share of the
-// products (cut at C block boundaries, so every C block has one owner).  The
-// wave then walks its products as one stream: operands of the next two
-// products are in flight while the current one is multiplied, across C block
-// boundaries, and C_in values of a block are fetched when the block starts.
-//
-// Lane l = 16*s + 4*rho + gam: K slice s (inner indices t = s, s+4, ..., s+20
-// of every product), tile rows 6*rho..6*rho+5, tile columns 6*gam..6*gam+5.
-// A product is staged through a wave-private LDS buffer, A transposed (a lane
-// reads its 6 rows of column t as three 16-byte loads) and B as is, both with
-// a padded row stride.  Pads (row/column 23, inner index 23) stay zero.  At
-// the end of a C block the four K slices are summed with cross-lane swaps,
-// leaving 9 of the 36 tile outputs in each lane.
+// Square blocks of edge S in [17, 24] (the 23x23 molecule blocks), padded to
+// a 24x24 tile.
 // ---------------------------------------------------------------------------
 constexpr int kTileEdge = 24;
-constexpr int kTileStride = 26;                       // doubles per LDS row
-constexpr int kTileOperand = kTileEdge * kTileStride; // doubles per staged operand
-
-__device__ __forceinline__ void swap_halves32(double& lo, double& hi) {
-  // lanes 0-31 end with (lo, partner lo), lanes 32-63 with (partner hi, hi)
-  const unsigned long long l = __double_as_longlong(lo), h = __double_as_longlong(hi);
-  const auto r0 = __builtin_amdgcn_permlane32_swap((unsigned)l, (unsigned)h, false, false);
-  const auto r1 = __builtin_amdgcn_permlane32_swap((unsigned)(l >> 32), (unsigned)(h >> 32), false, false);
-  lo = __longlong_as_double((long long)(((unsigned long long)r1[0] << 32) | r0[0]));
-  hi = __longlong_as_double((long long)(((unsigned long long)r1[1] << 32) | r0[1]));
-}
-
-__device__ __forceinline__ void swap_halves16(double& lo, double& hi) {
-  // within each 32-lane half: lanes 0-15 end with (lo, partner lo), lanes 16-31 with (partner hi, hi)
-  const unsigned long long l = __double_as_longlong(lo), h = __double_as_longlong(hi);
-  const auto r0 = __builtin_amdgcn_permlane16_swap((unsigned)l, (unsigned)h, false, false);
-  const auto r1 = __builtin_amdgcn_permlane16_swap((unsigned)(l >> 32), (unsigned)(h >> 32), false, false);
-  lo = __longlong_as_double((long long)(((unsigned long long)r1[0] << 32) | r0[0]));
-  hi = __longlong_as_double((long long)(((unsigned long long)r1[1] << 32) | r0[1]));
-}
-
-__device__ __forceinline__ int64_t uniform64(int64_t x) {
-  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
 
 // First c in [0, n] with prod_ptr[c] >= t (prod_ptr is non-decreasing).
 __device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_t n, int64_t t) {
@@ -247,251 +206,14 @@ __device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_
   return lo;
 }
 
-template <int S>
-__global__ __launch_bounds__(256, 2) void k_numeric_tile24(
-    const double* __restrict__ Av, const double* __restrict__ Bv, const double* __restrict__ Ov,
-    const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
-    const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals, int use_old,
-    double alpha, double beta) {
-  static_assert(S >= 13 && S <= kTileEdge, "tile kernel covers edges 13..24");
-  constexpr int NE = S * S;
-  constexpr int PER = (NE + 63) / 64;
-  constexpr int LAST = NE - 64 * (PER - 1);
-  // per wave: two stages, each A^T then B
-  __shared__ double lds[4][2][2 * kTileOperand];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int x = lane; x < 4 * kTileOperand; x += 64) (&lds[wv][0][0])[x] = 0.0;
-
-  // LDS offset (doubles, within a stage) of element e = lane + 64u of a
-  // product: A transposed, B as is
-  int offA[PER], offB[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = (u < PER - 1 || lane < LAST) ? lane + 64 * u : 0;
-    const int r = e / S, c = e - r * S;
-    offA[u] = c * kTileStride + r;
-    offB[u] = kTileOperand + r * kTileStride + c;
-  }
-  const bool tail = lane < LAST;
-  const int s = lane >> 4;
-  const int rho = (lane >> 2) & 3;
-  const int gam = lane & 3;
-  const int aoff = s * kTileStride + 6 * rho;
-  const int boff = kTileOperand + s * kTileStride + 6 * gam;
-
-  // Schedule.  Workgroups are dispatched round-robin over the 8 XCDs, so
-  // workgroup b runs on XCD b % 8.  Each XCD owns a contiguous run of C
-  // blocks holding 1/8 of the products; its waves take chunks of kChunk
-  // consecutive C blocks, interleaved, so at any time the XCD works on a few
-  // consecutive C block rows and their A blocks stay in its L2.
-  constexpr int kXcds = 8;
-  constexpr int kChunk = 2;
-  const int32_t xcd = blockIdx.x % kXcds;
-  const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;  // waves per XCD
-  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
-  const int32_t nnzc = live_nnzc(totals);
-  if (nnzc == 0) return;
-  const int64_t P = prod_ptr[nnzc];
-  const int32_t X0 = lower_bound_c(prod_ptr, nnzc, P * xcd / kXcds);
-  const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_c(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
-
-  // Index cursor: walks this wave's product stream (chunk by chunk) ahead of
-  // the operand fetch; the indices of the next two products wait in a queue.
-  int32_t iq = wix;
-  int64_t ip = 0, ip_end = 0;
-  if (X0 + (int64_t)iq * kChunk < X1) {
-    const int32_t c0 = X0 + iq * kChunk;
-    ip = prod_ptr[c0];
-    ip_end = prod_ptr[min(c0 + kChunk, X1)];
-  }
-  auto next_index = [&]() -> int64_t {
-    while (ip >= ip_end) {
-      iq += wpx;
-      if (X0 + (int64_t)iq * kChunk >= X1) return -1;
-      const int32_t c0 = X0 + iq * kChunk;
-      ip = prod_ptr[c0];
-      ip_end = prod_ptr[min(c0 + kChunk, X1)];
-    }
-    return ip++;
-  };
-  int32_t qa0 = -1, qb0 = -1, qa1 = -1, qb1 = -1;  // queue: next product, the one after
-  {
-    const int64_t n0 = next_index();
-    if (n0 >= 0) {
-      qa0 = prod_a[n0];
-      qb0 = prod_b[n0];
-    }
-    const int64_t n1 = next_index();
-    if (n1 >= 0) {
-      qa1 = prod_a[n1];
-      qb1 = prod_b[n1];
-    }
-  }
-  double opa[PER], opb[PER];
-  // issue the operand loads of the queue front and advance the queue
-  auto fetch_next = [&]() {
-    if (qa0 >= 0) {
-      const double* Ab = Av + (int64_t)qa0 * NE + lane;
-      const double* Bb = Bv + (int64_t)qb0 * NE + lane;
-#pragma unroll
-      for (int u = 0; u < PER - 1; ++u) {
-        opa[u] = Ab[64 * u];
-        opb[u] = Bb[64 * u];
-      }
-      opa[PER - 1] = tail ? Ab[64 * (PER - 1)] : 0.0;
-      opb[PER - 1] = tail ? Bb[64 * (PER - 1)] : 0.0;
-    }
-    qa0 = qa1;
-    qb0 = qb1;
-    const int64_t n = next_index();
-    qa1 = n >= 0 ? prod_a[n] : -1;
-    qb1 = n >= 0 ? prod_b[n] : -1;
-  };
-  auto stage_write = [&](const int st) {
-    double* base = &lds[wv][st][0];
-#pragma unroll
-    for (int u = 0; u < PER - 1; ++u) {
-      base[offA[u]] = opa[u];
-      base[offB[u]] = opb[u];
-    }
-    if (tail) {
-      base[offA[PER - 1]] = opa[PER - 1];
-      base[offB[PER - 1]] = opb[PER - 1];
-    }
-  };
-
-  // Pipeline: product n is fetched at step n-2, written to LDS stage n&1 at
-  // step n-1 and multiplied at step n.
-  const bool any = qa0 >= 0;
-  if (any) {
-    fetch_next();
-    stage_write(0);
-    fetch_next();
-  }
-  double acc[36];
-  auto step = [&](auto stage) {
-    constexpr int st = decltype(stage)::value;
-    stage_write(st ^ 1);
-    fetch_next();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const double* base = &lds[wv][st][0];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const double2* ap = reinterpret_cast<const double2*>(base + aoff + 4 * q * kTileStride);
-      const double2* bp = reinterpret_cast<const double2*>(base + boff + 4 * q * kTileStride);
-      double a[6], b[6];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double2 va = ap[k], vb = bp[k];
-        a[2 * k] = va.x;
-        a[2 * k + 1] = va.y;
-        b[2 * k] = vb.x;
-        b[2 * k + 1] = vb.y;
-      }
-#pragma unroll
-      for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[6 * i + j] = fma(a[i], b[j], acc[6 * i + j]);
-    }
-  };
-
-  // Compute cursor: current C block c (chunk ends at c1), next product p,
-  // end of c's products pe.  Walks the same stream as the index cursor.
-  int32_t cq = wix;
-  int32_t c = 0, c1 = 0;
-  int64_t p = 0, pe = 0;
-  if (X0 + (int64_t)cq * kChunk >= X1) return;
-  c = X0 + cq * kChunk;
-  c1 = min(c + kChunk, X1);
-  p = prod_ptr[c];
-  pe = prod_ptr[c + 1];
-#pragma unroll
-  for (int x = 0; x < 36; ++x) acc[x] = 0.0;
-
-  // Finish every C block that ends at p (blocks without products included):
-  // sum the four K slices, apply alpha, park the block row-major in the LDS
-  // stage that is free (`freestage`), then add beta*C_in and store it with
-  // contiguous, coalesced accesses.  Returns false when the wave has no
-  // products left.
-  auto advance = [&](auto freestage) -> bool {
-    constexpr int fs = decltype(freestage)::value;
-    double* const tile = &lds[wv][fs][0];
-    while (p == pe) {
-#pragma unroll
-      for (int x = 0; x < 18; ++x) {
-        swap_halves32(acc[x], acc[x + 18]);
-        acc[x] = acc[x] + acc[x + 18];
-      }
-#pragma unroll
-      for (int x = 0; x < 9; ++x) {
-        swap_halves16(acc[x], acc[x + 9]);
-        acc[x] = acc[x] + acc[x + 9];
-      }
-      // this lane's outputs are tile slots y = 9*s + x
-#pragma unroll
-      for (int x = 0; x < 9; ++x) {
-        const int y = 9 * s + x;
-        const int R = 6 * rho + y / 6, Cc = 6 * gam + y % 6;
-        if (R < S && Cc < S) tile[R * S + Cc] = alpha * acc[x];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int32_t o = use_old ? c_old_idx[c] : -1;
-      double* out = Cv + (int64_t)c * NE + lane;
-      const double* tl = tile + lane;
-      if (o >= 0) {
-        const double* ov = Ov + (int64_t)o * NE + lane;
-        double ol[PER];
-#pragma unroll
-        for (int u = 0; u < PER - 1; ++u) ol[u] = ov[64 * u];
-        ol[PER - 1] = tail ? ov[64 * (PER - 1)] : 0.0;
-#pragma unroll
-        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u] + beta * ol[u];
-        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)] + beta * ol[PER - 1];
-      } else {
-#pragma unroll
-        for (int u = 0; u < PER - 1; ++u) out[64 * u] = tl[64 * u];
-        if (tail) out[64 * (PER - 1)] = tl[64 * (PER - 1)];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int x = 0; x < 36; ++x) acc[x] = 0.0;
-      ++c;
-      if (c == c1) {
-        cq += wpx;
-        if (X0 + (int64_t)cq * kChunk >= X1) return false;
-        c = X0 + cq * kChunk;
-        c1 = min(c + kChunk, X1);
-        p = prod_ptr[c];
-      }
-      pe = prod_ptr[c + 1];
-    }
-    return true;
-  };
-
-  // products alternate between LDS stage 0 and stage 1; a block that ends
-  // after a stage-s product is finished in stage s, which is free by then
-  for (;;) {
-    if (p == pe && !advance(std::integral_constant<int, 1>())) break;
-    step(std::integral_constant<int, 0>());
-    ++p;
-    if (p == pe && !advance(std::integral_constant<int, 0>())) break;
-    step(std::integral_constant<int, 1>());
-    ++p;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Square blocks of edge S in [17, 24] on the FP64 matrix cores
 // (v_mfma_f64_4x4x4_4b: four independent 4x4x4 products per instruction, which
-// pad a 23-edge only to 24).  Same schedule as k_numeric_tile24 (one wave per
-// C block at a time, products as one stream per wave, two LDS stages); only
-// the block product and the block finish differ.
+// pad a 23-edge only to 24).  One wave per C block at a time; the product
+// stack is one flat array ordered by C block: each XCD (workgroup b runs on
+// XCD b mod 8) owns a contiguous run of C blocks with 1/8 of the products, its
+// waves take interleaved chunks of two C blocks and walk their products as one
+// stream (operands of the next product in registers, two LDS stages).
 //
 // Instruction layout (measured on the device): lane 16k + 4b + i holds
 // A_b[i][k] and B_b[k][i'] with i' = i, and the result lane 16i + 4b + j holds
