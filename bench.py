@@ -134,7 +134,7 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
         dA, dB, dCin = (bsmm.Matrix.from_csr(x, stream) for x in (w.A, w.B, w.C_old))
         dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
         # the autotuner picks the small-block variant for this edge (untimed)
-        variant = bsmm.bsmm_tune_small(1.0, dA.handle, dB.handle, 1.0, dCin.handle, dC.handle, 0.0, 2, stream)[0]
+        variants = bsmm.bsmm_tune_small(1.0, dA.handle, dB.handle, 1.0, dCin.handle, dC.handle, 0.0, 2, stream)[0]
         for _ in range(warmup):
             bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC, 0.0, stream=stream)
         torch.cuda.synchronize()
@@ -148,7 +148,7 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
         st = bsmm.bsmm_stats(dC.handle)
         num_ms = ph["numeric"] / max(n, 1)
         flops = st["useful_flops"]
-        row = {"edge": s, "blocks": nblocks, "path": PATH_NAMES.get(st["path"], st["path"]), "variant": variant,
+        row = {"edge": s, "blocks": nblocks, "path": PATH_NAMES.get(st["path"], st["path"]), "variants": variants,
                "ms": round(ms, 4), "gflops": round(flops / ms / 1e6, 1),
                "numeric_ms": round(num_ms, 4), "numeric_gflops": round(flops / num_ms / 1e6, 1),
                "numeric_gbs": round(8 * 4 * s * s * nblocks / num_ms / 1e6, 1)}
@@ -259,7 +259,7 @@ def small_class_leg(w, dA, dB, dCin, dC, stream, reps=5):
     from paper_1708_03604_amd import bsmm
     v, ms = bsmm.bsmm_tune_small(w.alpha, dA.handle, dB.handle, w.beta, dCin.handle if dCin is not None else None,
                                  dC.handle, w.eps, reps, stream)
-    if v < 0:
+    if v[0] < 0:
         return None
     st = dC.stack(stream)
     rp, ci, _ = dC.to_host(stream)
@@ -273,7 +273,7 @@ def small_class_leg(w, dA, dB, dCin, dC, stream, reps=5):
     for c in range(4):
         sel = cls == c
         fl = float(np.sum(2 * m[sel] * n[sel] * k[sel]))
-        t = ms[v, c] / reps
+        t = ms[v[c], c] / reps
         triples = {}
         for mm, nn, kk in set(zip(m[sel].tolist(), n[sel].tolist(), k[sel].tolist())):
             s2 = sel & (m == mm) & (n == nn) & (k == kk)
@@ -281,8 +281,10 @@ def small_class_leg(w, dA, dB, dCin, dC, stream, reps=5):
         classes.append({"class": names[c], "products": int(sel.sum()), "gflop": round(fl / 1e9, 4),
                         "ms": round(t, 4), "gflops": round(fl / t / 1e6, 1) if t > 0 else None,
                         "triples": dict(sorted(triples.items()))})
-    return {"variant": int(v), "depths": bsmm.bsmm_small_variant(v), "note": "each class timed alone (launch of "
-            "the whole grid over that class's list), mean of the tuner's launches", "classes": classes}
+    return {"variants": [int(x) for x in v], "depths": [bsmm.bsmm_small_variant(x)[c] for c, x in enumerate(v)],
+            "note": "each class timed alone with its tuned variant (launch of the whole grid over that class's "
+                    "list), mean of the tuner's launches; depth 16 + d is the FP64 matrix-core form",
+            "classes": classes}
 
 
 def _time_precision(w, dA, dB, dCin, stream, steps, warmup, prec):

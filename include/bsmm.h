@@ -85,7 +85,7 @@ enum {
 };
 
 /* Number of compiled pipeline variants of the small-block path. */
-#define BSMM_SMALL_VARIANTS 6
+#define BSMM_SMALL_VARIANTS 8
 
 /* Counters of the last multiply that wrote a handle. */
 typedef struct {
@@ -95,7 +95,8 @@ typedef struct {
   int64_t nvals;       /* values in the result */
   double useful_flops; /* sum over kept products of 2*m*n*k */
   int32_t path;        /* BSMM_PATH_* */
-  int32_t variant;     /* small-block pipeline variant used (-1 on other paths) */
+  int32_t variants[4]; /* small-block variant used per shape class 8x8, 8x16, 16x8, 16x16
+                          (-1 on other paths) */
 } bsmm_mult_stats;
 
 /*
@@ -214,39 +215,46 @@ bsmm_status bsmm_stats(bsmm_mat C, bsmm_mult_stats* out);
 /*
  * Autotuner of the small-block path (Section 2: the batched multiply is tuned
  * for each set of block dimensions).  The path pads each block to a shape
- * class, 8 or 16 rows by 8 or 16 columns, and keeps a number of block
- * products in flight per wave; a pipeline variant fixes that number per
- * class (bsmm_small_variant).  The tuning table maps a tuning key (the block
- * edges present in A's rows, A's columns and B's columns) to a variant;
- * multiplies whose key has no entry use variant 1.
+ * class, 8 or 16 rows by 8 or 16 columns; a variant fixes, per class, the
+ * form of the block product (FP64 vector units or FP64 matrix cores) and the
+ * number of block products in flight per wave (bsmm_small_variant).  The
+ * tuning table maps a tuning key (the block edges present in A's rows, A's
+ * columns and B's columns) to one variant per class; classes of a multiply
+ * whose key has no entry use variant 1.  Classes that share a variant run in
+ * one launch.
  *
  * bsmm_tune_small computes C_out = alpha*A*B + beta*C_in exactly as
  * bsmm_multiply with BSMM_FP64 does, then, if the small-block path served it,
  * times the products of each class alone with every variant (`reps` launches
- * each, HIP events on `stream`), enters the variant with the least total time
- * into the table and leaves C_out as that variant computes it (variants
- * with the same forms give identical values; the forms add in different
- * orders, all within FP64 rounding of the exact sum).
+ * each, HIP events on `stream`), enters for each class the variant with the
+ * least time into the table and leaves C_out as those variants compute it
+ * (variants of the same form give identical values; the forms add in
+ * different orders, all within FP64 rounding of the exact sum).
  * Arguments as bsmm_multiply, plus:
- *   reps        : launches per variant and class, 1 ..  1000
- *   variant_out : chosen variant, or -1 when another path serves these sizes
- *                 (then nothing is timed and the table is unchanged)
- *   ms_out      : NULL, or host array [BSMM_SMALL_VARIANTS * 4] receiving
- *                 the milliseconds of variant v, class c at [4*v + c],
- *                 summed over the reps (0 for a variant that does not serve
- *                 these block edges)
+ *   reps         : launches per variant and class, 1 ..  1000
+ *   variants_out : host array [4]: chosen variant per class, or all -1 when
+ *                  another path serves these sizes (then nothing is timed and
+ *                  the table is unchanged)
+ *   ms_out       : NULL, or host array [BSMM_SMALL_VARIANTS * 4] receiving
+ *                  the milliseconds of variant v, class c at [4*v + c],
+ *                  summed over the reps (0 for a variant that does not serve
+ *                  these block edges)
  * C_in must not be C_out (BSMM_E_ARG), and C_out must not be reserved.
  * Synchronises `stream`.
  */
 bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C_out,
-                            double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream);
+                            double filter_eps, int32_t reps, int32_t* variants_out, double* ms_out, void* stream);
 
-/* Products kept in flight per wave by variant v in the classes 8x8, 8x16,
- * 16x8 and 16x16 (rows x columns) into depths[4]; 1 means several products
- * of one C block per step (four for 8x8, one per 16-lane group; two for 8x16
- * and 16x8, one per 32-lane group); 8 means two such steps of the 8x8 class
- * in flight, which only serves block edges of at most 8 (multiplies with
- * larger edges use variant 1 instead).  BSMM_E_ARG if v is out of range. */
+/* Form and depth of variant v in the classes 8x8, 8x16, 16x8 and 16x16 (rows
+ * x columns) into depths[4].  On the vector units: the products kept in
+ * flight per wave, where 1 means several products of one C block per step
+ * (four for 8x8, one per 16-lane group; two for 8x16 and 16x8, one per
+ * 32-lane group) and 8 two such steps of the 8x8 class, which only serves
+ * block edges of at most 8 (multiplies with larger edges use variant 1 for
+ * that class instead).  16 + d: the FP64 matrix-core form
+ * (v_mfma_f64_4x4x4_4b, the block padded to 4x4 tiles and the inner index to
+ * a multiple of 8) with d products in flight.  BSMM_E_ARG if v is out of
+ * range. */
 bsmm_status bsmm_small_variant(int32_t v, int32_t* depths);
 
 /* Tuning key of the product A*B: bits e-1, 16+e-1 and 32+e-1 are set for each
@@ -255,14 +263,16 @@ bsmm_status bsmm_small_variant(int32_t v, int32_t* depths);
  * serve such sizes). */
 bsmm_status bsmm_tune_key(bsmm_mat A, bsmm_mat B, uint64_t* key);
 
-/* Table entry of `key`: bsmm_tune_set enters `variant` (0 .. BSMM_SMALL_VARIANTS-1)
- * or removes the entry (variant < 0); bsmm_tune_get returns it, -1 if none.
+/* Table entry of `key`: bsmm_tune_set enters variants[4] (one per class, each
+ * 0 .. BSMM_SMALL_VARIANTS-1) or removes the entry (variants NULL);
+ * bsmm_tune_get writes the entry into variants[4], all -1 if there is none.
  * The table is process-wide and guarded by a lock. */
-bsmm_status bsmm_tune_set(uint64_t key, int32_t variant);
-bsmm_status bsmm_tune_get(uint64_t key, int32_t* variant);
+bsmm_status bsmm_tune_set(uint64_t key, const int32_t* variants);
+bsmm_status bsmm_tune_get(uint64_t key, int32_t* variants);
 
-/* Copy up to `cap` table entries (ascending key) into keys[] / variants[]
- * (host arrays); *n receives the number of entries in the table. */
+/* Copy up to `cap` table entries (ascending key) into keys[cap] and
+ * variants[4*cap] (host arrays); *n receives the number of entries in the
+ * table. */
 bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, int32_t* n);
 
 /*

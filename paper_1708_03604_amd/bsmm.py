@@ -29,7 +29,7 @@ BSMM_PATH_TILE23 = 1
 BSMM_PATH_SMALL = 2
 BSMM_PATH_SPLIT23 = 3
 BSMM_PATH_SLICE23 = 4
-BSMM_SMALL_VARIANTS = 6
+BSMM_SMALL_VARIANTS = 8
 
 
 class BsmmError(RuntimeError):
@@ -42,7 +42,7 @@ class BsmmError(RuntimeError):
 class MultStats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("products", ctypes.c_int64), ("nnzb", ctypes.c_int64),
                 ("nvals", ctypes.c_int64), ("useful_flops", ctypes.c_double), ("path", ctypes.c_int32),
-                ("variant", ctypes.c_int32)]
+                ("variants", ctypes.c_int32 * 4)]
 
 
 # every function declared in include/bsmm.h, with its ctypes signature
@@ -71,7 +71,7 @@ SIGNATURES = {
     "bsmm_tune_small": ([_dbl, _vp, _vp, _dbl, _vp, _vp, _dbl, _i32, _vp, _vp, _vp], _int),
     "bsmm_small_variant": ([_i32, _vp], _int),
     "bsmm_tune_key": ([_vp, _vp, _vp], _int),
-    "bsmm_tune_set": ([_u64, _i32], _int),
+    "bsmm_tune_set": ([_u64, _vp], _int),
     "bsmm_tune_get": ([_u64, _vp], _int),
     "bsmm_tune_entries": ([_vp, _vp, _i32, _vp], _int),
 }
@@ -200,7 +200,7 @@ def bsmm_export_stack(C, st_c, st_a, st_b, ptr_kind=None, stream=None):
 def bsmm_stats(C):
     s = MultStats()
     _check("bsmm_stats", lib().bsmm_stats(C, ctypes.byref(s)))
-    return {f: getattr(s, f) for f, _ in MultStats._fields_}
+    return {f: (list(getattr(s, f)) if f == "variants" else getattr(s, f)) for f, _ in MultStats._fields_}
 
 
 PHASES = ("norms", "count", "sizing", "fill", "numeric", "total")
@@ -250,12 +250,13 @@ def bsmm_graph_destroy(g):
 
 
 def bsmm_tune_small(alpha, A, B, beta, C_in, C_out, filter_eps, reps=5, stream=None):
-    """Returns (chosen variant or -1, per variant and class milliseconds [6, 4])."""
-    v = ctypes.c_int32()
+    """Returns (chosen variant per class, a list of 4 (all -1 if another path
+    serves the sizes), per variant and class milliseconds [BSMM_SMALL_VARIANTS, 4])."""
+    v = np.zeros(4, dtype=np.int32)
     ms = np.zeros((BSMM_SMALL_VARIANTS, 4), dtype=np.float64)
     _check("bsmm_tune_small", lib().bsmm_tune_small(float(alpha), A, B, float(beta), C_in, C_out, float(filter_eps),
-                                                    int(reps), ctypes.byref(v), ms.ctypes.data, _stream(stream)))
-    return v.value, ms
+                                                    int(reps), v.ctypes.data, ms.ctypes.data, _stream(stream)))
+    return v.tolist(), ms
 
 
 def bsmm_small_variant(v):
@@ -270,23 +271,31 @@ def bsmm_tune_key(A, B):
     return k.value
 
 
-def bsmm_tune_set(key, variant):
-    _check("bsmm_tune_set", lib().bsmm_tune_set(int(key), int(variant)))
+def bsmm_tune_set(key, variants):
+    """Enter one variant per class (a sequence of 4), or remove the entry (None)."""
+    if variants is None:
+        _check("bsmm_tune_set", lib().bsmm_tune_set(int(key), None))
+        return
+    v = np.ascontiguousarray(variants, dtype=np.int32)
+    if v.shape != (4,):
+        raise ValueError("one variant per class: 4 values")
+    _check("bsmm_tune_set", lib().bsmm_tune_set(int(key), v.ctypes.data))
 
 
 def bsmm_tune_get(key):
-    v = ctypes.c_int32()
-    _check("bsmm_tune_get", lib().bsmm_tune_get(int(key), ctypes.byref(v)))
-    return v.value
+    """The entry's variants per class (a list of 4), all -1 if there is none."""
+    v = np.zeros(4, dtype=np.int32)
+    _check("bsmm_tune_get", lib().bsmm_tune_get(int(key), v.ctypes.data))
+    return v.tolist()
 
 
 def bsmm_tune_entries():
     n = ctypes.c_int32()
     _check("bsmm_tune_entries", lib().bsmm_tune_entries(None, None, 0, ctypes.byref(n)))
     keys = np.zeros(max(n.value, 1), dtype=np.uint64)
-    vs = np.zeros(max(n.value, 1), dtype=np.int32)
+    vs = np.zeros((max(n.value, 1), 4), dtype=np.int32)
     _check("bsmm_tune_entries", lib().bsmm_tune_entries(keys.ctypes.data, vs.ctypes.data, n.value, ctypes.byref(n)))
-    return dict(zip(keys[:n.value].tolist(), vs[:n.value].tolist()))
+    return {k: v.tolist() for k, v in zip(keys[:n.value].tolist(), vs[:n.value])}
 
 
 # ------------------------------------------------------------ convenience

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -228,7 +229,7 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
     m->nprod = 0;
     m->has_stack = false;
     m->stats = bsmm_mult_stats{};
-    m->stats.variant = -1;
+    std::fill(m->stats.variants, m->stats.variants + 4, -1);
     const int64_t zero[3] = {0, 0, 0};
     HIP_TRY(hipMemsetAsync(m->cur.row_ptr.p, 0, sizeof(int32_t) * (m->nbrows + 1), s));
     HIP_TRY(hipMemsetAsync(m->cur.blk_off.p, 0, sizeof(int64_t), s));
@@ -262,7 +263,7 @@ bsmm_status empty_result(bsmm_matrix* C, hipStream_t s, bsmm_status code, const 
   C->nprod = 0;
   C->has_stack = false;
   C->stats = bsmm_mult_stats{};
-  C->stats.variant = -1;
+  std::fill(C->stats.variants, C->stats.variants + 4, -1);
   const int64_t zero[4] = {0, 0, 0, 0};
   if (ensure_storage(C->cur, C->nbrows, 0, 0) == hipSuccess &&
       hipMemsetAsync(C->cur.row_ptr.p, 0, sizeof(int32_t) * (C->nbrows + 1), s) == hipSuccess &&
@@ -272,19 +273,28 @@ bsmm_status empty_result(bsmm_matrix* C, hipStream_t s, bsmm_status code, const 
   return fail(code, msg + " (the result matrix was left empty)");
 }
 
-// Tuning table of the small-block path: tuning key -> pipeline variant.
+// Tuning table of the small-block path: tuning key -> variant per shape class.
+using ClassVariants = std::array<int32_t, 4>;
 std::mutex g_tune_mu;
-std::map<uint64_t, int32_t> g_tune;
+std::map<uint64_t, ClassVariants> g_tune;
 
 uint64_t tune_key(const bsmm_matrix* A, const bsmm_matrix* B) {
   return (uint64_t)(A->row_edges & 0xffffu) | (uint64_t)(A->col_edges & 0xffffu) << 16 |
          (uint64_t)(B->col_edges & 0xffffu) << 32;
 }
 
-int32_t tuned_variant(uint64_t key) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(key);
-  return it == g_tune.end() ? kSmallDefault : it->second;
+// Variants per class for a multiply with key `key` and largest block edge
+// `edge` (a variant that does not serve the edge falls back to the default).
+ClassVariants tuned_variants(uint64_t key, int32_t edge) {
+  ClassVariants v{kSmallDefault, kSmallDefault, kSmallDefault, kSmallDefault};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) v = it->second;
+  }
+  for (auto& x : v)
+    if (edge > small_variant_max_edge(x)) x = kSmallDefault;
+  return v;
 }
 
 struct EventPair {
@@ -296,6 +306,22 @@ struct EventPair {
 };
 
 }  // namespace
+
+// One small-block launch per distinct variant, over the classes that use it.
+hipError_t launch_small_plan(const NumArgs& na, const bsmm_matrix* C, const ClassVariants& v, hipStream_t s) {
+  int32_t done = 0;
+  for (int c = 0; c < 4; ++c) {
+    if (done & (1 << c)) continue;
+    int32_t mask = 0;
+    for (int d = c; d < 4; ++d)
+      if (v[d] == v[c]) mask |= 1 << d;
+    done |= mask;
+    const hipError_t e =
+        launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, v[c], mask, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 extern "C" {
 
@@ -348,7 +374,7 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
   for (int32_t j = 0; j < nbcols; ++j) m->max_edge = std::max(m->max_edge, col_sizes[j]);
   for (int32_t i = 0; i < nbrows; ++i) m->row_edges |= 1u << (std::min(row_sizes[i], 32) - 1);
   for (int32_t j = 0; j < nbcols; ++j) m->col_edges |= 1u << (std::min(col_sizes[j], 32) - 1);
-  m->stats.variant = -1;
+  std::fill(m->stats.variants, m->stats.variants + 4, -1);
   m->nnzb = nnzb;
   m->nvals = nvals;
   auto cleanup = [&](bsmm_status code, const std::string& msg) {
@@ -755,7 +781,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_a = C->prod_a.p;
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
-  int32_t variant = -1;
+  na.wide_inner = (A->col_edges & 0x7fffu) == 0;  // no inner block edge below 16
+  ClassVariants variants{-1, -1, -1, -1};
   if (split) {
     HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
     HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
@@ -770,10 +797,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   } else if (small) {
     HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
-    variant = tuned_variant(tune_key(A, B));
-    if (std::max(A->max_edge, B->max_edge) > small_variant_max_edge(variant)) variant = kSmallDefault;
-    HIP_W(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, variant,
-                                 kSmallAllClasses, s));
+    variants = tuned_variants(tune_key(A, B), std::max(A->max_edge, B->max_edge));
+    HIP_W(launch_small_plan(na, C, variants, s));
     C->small_args = na;
   } else {
     HIP_W(launch_numeric(na, uniform, C->work.p, s));
@@ -785,7 +810,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   if (in_place) std::swap(C->cur, C->spare);
   C->has_stack = true;
   C->stats.path = split ? BSMM_PATH_SPLIT23 : slice ? BSMM_PATH_SLICE23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
-  C->stats.variant = variant;
+  std::copy(variants.begin(), variants.end(), C->stats.variants);
   if (reserved) return BSMM_OK;
   C->nnzb = (int32_t)nnzc;
   C->nvals = nvals;
@@ -1056,16 +1081,16 @@ bsmm_status bsmm_graph_destroy(bsmm_graph g) {
 }
 
 bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C,
-                            double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream) {
+                            double filter_eps, int32_t reps, int32_t* variants_out, double* ms_out, void* stream) {
   g_err.clear();
-  if (!variant_out) return fail(BSMM_E_ARG, "NULL variant_out");
+  if (!variants_out) return fail(BSMM_E_ARG, "NULL variants_out");
   if (reps < 1 || reps > 1000) return fail(BSMM_E_ARG, "reps must be in 1 .. 1000");
   if (C && C == C_in && beta != 0.0) return fail(BSMM_E_ARG, "tuning needs C_in distinct from C_out");
   if (C && C->cap_nnzb > 0) return fail(BSMM_E_ARG, "tuning does not take a reserved output");
   bsmm_status st = bsmm_multiply(alpha, A, B, beta, C_in, C, filter_eps, BSMM_FP64, stream);
   if (st != BSMM_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  *variant_out = -1;
+  std::fill(variants_out, variants_out + 4, -1);
   if (ms_out) std::fill(ms_out, ms_out + 4 * kSmallVariants, 0.0);
   if (C->stats.path != BSMM_PATH_SMALL) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -1077,14 +1102,11 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
   EventPair ev;
   HIP_TRY(hipEventCreate(&ev.e[0]));
   HIP_TRY(hipEventCreate(&ev.e[1]));
-  double total[kSmallVariants];
+  double best_ms[4] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, HUGE_VAL};
+  ClassVariants best{kSmallDefault, kSmallDefault, kSmallDefault, kSmallDefault};
   const int32_t edge = std::max(A->max_edge, B->max_edge);
   for (int32_t v = 0; v < kSmallVariants; ++v) {
-    total[v] = 0.0;
-    if (edge > small_variant_max_edge(v)) {  // not valid for these sizes: not timed
-      total[v] = HUGE_VAL;
-      continue;
-    }
+    if (edge > small_variant_max_edge(v)) continue;  // not valid for these sizes: not timed
     for (int c = 0; c < 4; ++c) {
       HIP_TRY(hipEventRecord(ev.e[0], s));
       for (int32_t r = 0; r < reps; ++r)
@@ -1094,22 +1116,21 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
       HIP_TRY(hipEventSynchronize(ev.e[1]));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
-      total[v] += ms;
       if (ms_out) ms_out[4 * v + c] = ms;
+      if (ms < best_ms[c]) {
+        best_ms[c] = ms;
+        best[c] = v;
+      }
     }
   }
-  int32_t best = kSmallDefault;
-  for (int32_t v = 0; v < kSmallVariants; ++v)
-    if (total[v] < total[best]) best = v;
-  HIP_TRY(launch_numeric_small(na, C->class_list.p, C->class_start.p, C->class_q.p, C->prod_desc.p, best,
-                               kSmallAllClasses, s));
+  HIP_TRY(launch_small_plan(na, C, best, s));
   HIP_TRY(hipStreamSynchronize(s));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(A, B)] = best;
   }
-  C->stats.variant = best;
-  *variant_out = best;
+  std::copy(best.begin(), best.end(), C->stats.variants);
+  std::copy(best.begin(), best.end(), variants_out);
   return BSMM_OK;
 }
 
@@ -1130,23 +1151,28 @@ bsmm_status bsmm_tune_key(bsmm_mat A, bsmm_mat B, uint64_t* key) {
   return BSMM_OK;
 }
 
-bsmm_status bsmm_tune_set(uint64_t key, int32_t variant) {
+bsmm_status bsmm_tune_set(uint64_t key, const int32_t* variants) {
   g_err.clear();
-  if (variant >= kSmallVariants) return fail(BSMM_E_ARG, "variant out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (variant < 0)
+  if (!variants) {
     g_tune.erase(key);
-  else
-    g_tune[key] = variant;
+    return BSMM_OK;
+  }
+  ClassVariants v;
+  for (int c = 0; c < 4; ++c) {
+    if (variants[c] < 0 || variants[c] >= kSmallVariants) return fail(BSMM_E_ARG, "variant out of range");
+    v[c] = variants[c];
+  }
+  g_tune[key] = v;
   return BSMM_OK;
 }
 
-bsmm_status bsmm_tune_get(uint64_t key, int32_t* variant) {
+bsmm_status bsmm_tune_get(uint64_t key, int32_t* variants) {
   g_err.clear();
-  if (!variant) return fail(BSMM_E_ARG, "NULL variant");
+  if (!variants) return fail(BSMM_E_ARG, "NULL variants");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(key);
-  *variant = it == g_tune.end() ? -1 : it->second;
+  for (int c = 0; c < 4; ++c) variants[c] = it == g_tune.end() ? -1 : it->second[c];
   return BSMM_OK;
 }
 
@@ -1158,7 +1184,7 @@ bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, in
   for (const auto& kv : g_tune) {
     if (i >= cap) break;
     keys[i] = kv.first;
-    variants[i] = kv.second;
+    for (int c = 0; c < 4; ++c) variants[4 * i + c] = kv.second[c];
     ++i;
   }
   *n = (int32_t)g_tune.size();

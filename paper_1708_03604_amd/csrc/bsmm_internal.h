@@ -104,6 +104,7 @@ struct NumArgs {
   const int32_t* prod_a;
   const int32_t* prod_b;
   double* c_values;
+  int wide_inner;          // every inner block edge >= 16: the generic path may use the matrix-core form
 };
 
 // Launchers (all enqueue on `s`; they return the launch status).
@@ -153,13 +154,14 @@ int64_t class_list_tmp_elems(int64_t nnzc_bound);  // entries of cnt and cnt_pre
 int64_t class_entries(int64_t nnzc_bound);
 hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, int64_t* tmp, int4* list,
                               int32_t* cls_start, int64_t* cnp, int64_t* qstart, int4* desc, hipStream_t s);
-// Pipeline variants of the small-block kernel: variant v keeps
-// small_variant_depths(v)[c] products in flight in class c (1 means the
-// form with several products per step: four for 8x8, two for 8x16, 16x8;
-// 8 means two such steps of the 8x8 class, for block edges of at most 8).  `mask` selects
-// the classes to run (bit c = class c): all of them in a multiply, one at a
-// time when tuning.  kSmallDefault is the untuned choice.
-constexpr int32_t kSmallVariants = 6;
+// Variants of the small-block kernel: variant v runs class c in form and
+// depth small_variant_depths(v)[c]: on the vector units, 1 means the form
+// with several products per step (four for 8x8, two for 8x16, 16x8), 8 two
+// steps of the 8x8 class for block edges of at most 8, other values the
+// products in flight of the one-product form; 16 + d the FP64 matrix-core
+// form with d products in flight.  `mask` selects the classes to run (bit c
+// = class c).  kSmallDefault is the untuned choice.
+constexpr int32_t kSmallVariants = 8;
 constexpr int32_t kSmallDefault = 1;  // 8x8 class four products per step, 2 in flight for the others
 constexpr int32_t kSmallAllClasses = 15;
 void small_variant_depths(int32_t v, int32_t* depths);

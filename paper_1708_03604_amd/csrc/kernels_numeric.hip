@@ -17,13 +17,26 @@ namespace bsmm {
 // sub-tiles and every product into K chunks of at most 32; a sub-tile is
 // accumulated in registers over all chunks of all products of its C block.
 //
-// Lane l = 8*ty + tx owns sub-tile rows 4ty..4ty+3 and columns 4tx..4tx+3.
-// A chunk is staged through wave-private LDS: A transposed (row t holds
-// A(r, k0+t) for the sub-tile's rows) and B as is, both with a row stride of
-// kMidStride doubles, so a lane reads its 4 A values and 4 B values of inner
-// index t with two 16-byte loads each.  The loads of the next chunk are
-// issued before the current chunk is multiplied.  Rows and columns past the
-// block stay stale in LDS; the outputs they feed are never stored.
+// A chunk is staged through wave-private LDS with a row stride of kMidStride
+// doubles, zeros past the block and the chunk; the loads of the next chunk
+// are issued before the current chunk is multiplied.  Two forms multiply a
+// staged chunk, chosen per C block; both keep the sub-tile's 16 values per
+// lane in the same registers:
+//   - C blocks with both edges >= 16, in multiplies whose inner block edges
+//     are all >= 16: FP64 matrix cores, v_mfma_f64_4x4x4_4b
+//     as in the 23x23 kernel (lane 16k + 4b + i holds A_b[i][k] and B_b[k][i],
+//     result lane 16i + 4b + j holds D_b[i][j]).  The sub-tile is a 4x4 grid of
+//     8x8 super-tiles, each the 2x2 tiles of one instruction, one accumulator
+//     per super-tile; the inner index runs in pairs (slot k: t = 8p + 2k and
+//     t + 1), so A is staged as stored and B transposed and one 16-byte read
+//     gives a lane the operands of two instructions: per 8 inner indices,
+//     eight reads and 32 instructions.
+//     (The inner index is padded to a multiple of 8 there, while the vector
+//     form runs exactly k steps: with narrow inner blocks it is the faster.)
+//   - otherwise FP64 vector FMA, A staged transposed (row t holds A(r, k0+t))
+//     and B as is: lane l = 8*ty + tx owns sub-tile rows 4ty..4ty+3 and
+//     columns 4tx..4tx+3 and reads its 4 A values and 4 B values of inner
+//     index t with two 16-byte loads each.
 // ---------------------------------------------------------------------------
 constexpr int kMid = 32;
 constexpr int kMidStride = 34;  // doubles per LDS row: 16-byte aligned rows, 2-way write conflicts at most
@@ -90,6 +103,9 @@ __device__ __forceinline__ bool mid_next(const NumArgs& g, MidCursor& u, int32_t
   return true;
 }
 
+// WIDE: every inner block edge is >= 16 (the matrix-core form may run); the
+// other instantiation is the vector form alone.
+template <bool WIDE>
 __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
   __shared__ __align__(16) double lds[4][2 * kMidOperand];  // per wave: A^T, then B
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -121,11 +137,19 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
       rb[v] = (bcol && r < kk) ? bp[(int64_t)2 * v * u.n] : 0.0;
     }
   };
-  auto stage = [&]() {
+  auto stage = [&](bool mma) {
+    if (mma) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      As[lc * kMidStride + lr + 2 * v] = ra[v];
-      Bs[(lr + 2 * v) * kMidStride + lc] = rb[v];
+      for (int v = 0; v < 16; ++v) {
+        As[(lr + 2 * v) * kMidStride + lc] = ra[v];
+        Bs[lc * kMidStride + lr + 2 * v] = rb[v];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        As[lc * kMidStride + lr + 2 * v] = ra[v];
+        Bs[(lr + 2 * v) * kMidStride + lc] = rb[v];
+      }
     }
   };
   auto sync = [&]() {
@@ -143,38 +167,63 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
   for (;;) {
     // the chunk to multiply now is the one the fetch cursor points at
     const MidCursor cur = f;
+    const bool mma = WIDE && cur.m >= 16 && cur.n >= 16;  // uniform over the wave
     sync();
-    stage();
+    stage(mma);
     sync();
     const bool last = mid_next(g, f, nnzc, nwaves);
     if (f.valid) fetch(f);
     const int kk = max(0, min(kMid, cur.k - cur.k0));
-    const double* ap = As + 4 * ty;
-    const double* bp = Bs + 4 * tx;
+    if (mma) {
+      // acc[I][J]: super-tile (I, J); fragment lane roles as in the 23x23 kernel
+      const int fk = lane >> 4, fb = (lane >> 2) & 3, fi = lane & 3;
+      const double* ap = As + (4 * (fb >> 1) + fi) * kMidStride + 2 * fk;
+      const double* bp = Bs + (4 * (fb & 1) + fi) * kMidStride + 2 * fk;
+      for (int kp = 0; kp < (kk + 7) >> 3; ++kp) {
+        double2 a[4], b[4];
+#pragma unroll
+        for (int I = 0; I < 4; ++I) a[I] = *reinterpret_cast<const double2*>(ap + 8 * I * kMidStride + 8 * kp);
+#pragma unroll
+        for (int J = 0; J < 4; ++J) b[J] = *reinterpret_cast<const double2*>(bp + 8 * J * kMidStride + 8 * kp);
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+          for (int J = 0; J < 4; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I].x, b[J].x, acc[I][J], 0, 0, 0);
+#pragma unroll
+        for (int I = 0; I < 4; ++I)
+#pragma unroll
+          for (int J = 0; J < 4; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I].y, b[J].y, acc[I][J], 0, 0, 0);
+      }
+    } else {
+      const double* ap = As + 4 * ty;
+      const double* bp = Bs + 4 * tx;
 #pragma unroll 4
-    for (int t = 0; t < kk; ++t) {
-      const double2 a01 = *reinterpret_cast<const double2*>(ap + t * kMidStride);
-      const double2 a23 = *reinterpret_cast<const double2*>(ap + t * kMidStride + 2);
-      const double2 b01 = *reinterpret_cast<const double2*>(bp + t * kMidStride);
-      const double2 b23 = *reinterpret_cast<const double2*>(bp + t * kMidStride + 2);
-      const double a[4] = {a01.x, a01.y, a23.x, a23.y};
-      const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+      for (int t = 0; t < kk; ++t) {
+        const double2 a01 = *reinterpret_cast<const double2*>(ap + t * kMidStride);
+        const double2 a23 = *reinterpret_cast<const double2*>(ap + t * kMidStride + 2);
+        const double2 b01 = *reinterpret_cast<const double2*>(bp + t * kMidStride);
+        const double2 b23 = *reinterpret_cast<const double2*>(bp + t * kMidStride + 2);
+        const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+        const double b[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      }
     }
     if (last) {
-      // alpha * acc + beta * C_in, then store the lane's 4x4 outputs
+      // alpha * acc + beta * C_in, then store the lane's 16 outputs
       const int64_t off = g.c_blk_off[cur.c];
       const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
       const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = kMid * cur.ti + 4 * ty + i;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int cc = kMid * cur.tj + 4 * tx + j;
+          // matrix-core form: lane 16k + 4b + i' holds row 8I + 4(b >> 1) + k,
+          // column 8J + 4(b & 1) + i' of super-tile (I, J) = (i, j)
+          const int r = kMid * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : 4 * ty + i);
+          const int cc = kMid * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : 4 * tx + j);
           if (r < cur.m && cc < cur.n) {
             const int64_t e = (int64_t)r * cur.n + cc;
             double v = g.alpha * acc[i][j];
@@ -471,7 +520,10 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t blocks = (a.nnzc_bound + 3) / 4;  // every wave owns at least one C block at the start
   if (blocks > 2 * cus) blocks = 2 * cus;   // two workgroups of 4 waves per CU stay resident
-  hipLaunchKernelGGL(k_numeric_mid, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  if (a.wide_inner)
+    hipLaunchKernelGGL(k_numeric_mid<true>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_numeric_mid<false>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

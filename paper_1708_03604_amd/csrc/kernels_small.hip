@@ -866,6 +866,286 @@ __device__ __forceinline__ void small_multi(const SmallOps& P, double* __restric
   }
 }
 
+// FP64 matrix-core form: one product per step on v_mfma_f64_4x4x4_4b (four
+// independent 4x4x4 products per instruction).  The padded MP x NP C block is
+// a grid of 4x4 tiles, four per instruction (G = MP*NP/64 instructions per K
+// step): tile tau = 4g + b of instruction group g sits at tile row tau / (NP/4)
+// and tile column tau % (NP/4).  Lane 16kk + 4b + i holds A_b[i][kk] and
+// B_b[kk][i]; the result lane 16i + 4b + j holds D_b[i][j].  The inner index
+// runs in pairs so that one 16-byte LDS read gives a lane the operands of two
+// instructions (slot kk: t = 8kp + 2kk and t + 1), so k is padded to 8 or 16.
+// A product is staged in one LDS stage per wave: A as rows of stride kMmaS
+// doubles, B transposed (row c holds B(:, c)) with the same stride, and the
+// inner-index pads k .. kpad-1 of both written as zeros.  Rows past m and
+// columns past n stay stale: they only reach outputs that are never stored.
+// The C block is accumulated in G registers per lane and stored directly.
+constexpr int kMmaS = 18;  // even (16-byte pairs), and eight rows of one read fall on distinct banks
+// ceil(2^16 / x) for x = 1..16: (e * kInv16[x]) >> 16 = e / x for e < 256
+__constant__ uint32_t kInv16[17] = {0,    65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192,
+                                    7282, 6554,  5958,  5462,  5042,  4682,  4370,  4096};
+
+template <int MP, int NP, int D>
+__device__ __forceinline__ void small_mfma(const SmallOps& P, double* __restrict__ wl, int32_t L0, int32_t L1,
+                                           int32_t xcd, int32_t wpx, int32_t wix, int lane) {
+  constexpr int TN = NP / 4, G = MP * NP / 64;
+  constexpr int QA = MP * 16 / 64, QB = 16 * NP / 64;  // element loads per lane of the largest A and B (k = 16)
+  static_assert((MP + NP) * kMmaS <= 2 * kStage, "the stage fits the wave's LDS");
+  double* const As = wl;
+  double* const Bs = wl + MP * kMmaS;
+  const int kk = lane >> 4, bq = (lane >> 2) & 3, iq = lane & 3;
+
+  // This wave's run of the list: [E0, E1), products [Q0, Q0 + NQ) in list order.
+  const int64_t L = L1 - L0;
+  const int64_t X0 = L0 + L * xcd / kXcds, X1 = L0 + L * (xcd + 1) / kXcds;
+  const int32_t E0 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix));
+  const int32_t E1 = (int32_t)(X0 + wave_base(X1 - X0, wpx, wix + 1));
+  if (E0 >= E1) return;
+  const int64_t Q0 = P.qstart[E0];
+  const int32_t NQ = (int32_t)(P.qstart[E1] - Q0);
+  const int4* __restrict__ dq = P.desc + Q0;
+
+  // ---- entry batches: lane u holds entry eb + u (current) and eb + 64 + u (next)
+  int32_t eb = E0, ei = E0;
+  int4 ca, cb, na, nb;
+  auto load_entries = [&](int32_t base, int4& x, int4& y) {
+    const int64_t e = base + lane < E1 ? base + lane : E1 - 1;
+    x = P.list[2 * e];
+    y = P.list[2 * e + 1];
+  };
+  load_entries(eb, ca, cb);
+  settle(ca);
+  settle(cb);
+  load_entries(eb + 64, na, nb);
+  // ---- descriptor batches: lane u holds descriptor qb + u (current) and qb + 64 + u (next)
+  int32_t qb = 0, qi = 0;
+  int4 cd, nd;
+  auto load_desc = [&](int32_t base, int4& x) {
+    const int32_t q = base + lane < NQ ? base + lane : (NQ > 0 ? NQ - 1 : 0);
+    x = dq[q];
+  };
+  load_desc(qb, cd);
+  settle(cd);
+  load_desc(qb + 64, nd);
+
+  // ---- finishing data of the C blocks between fetch and finish: a queue in
+  // lanes (entry w at lane w mod 64; at most D+1 blocks are open at a time)
+  int32_t fifo_mn = 0, fifo_co0 = 0, fifo_co1 = 0, fifo_oo0 = 0, fifo_oo1 = 0;
+  int32_t fw = 0, fr = 0;
+
+  // ---- fetch cursor: current entry (m, n, products left)
+  bool fok = true;
+  int32_t fm = 0, fn = 0, frem = 0;
+  auto take_entry = [&]() {
+    const int u = ei - eb;
+    const int32_t mn = __builtin_amdgcn_readlane(ca.x, u);
+    fm = mn & 255;
+    fn = mn >> 8;
+    frem = __builtin_amdgcn_readlane(ca.z, u);
+    const bool mine = lane == (fw & 63);
+    fifo_mn = mine ? mn : fifo_mn;
+    fifo_co0 = mine ? __builtin_amdgcn_readlane(cb.x, u) : fifo_co0;
+    fifo_co1 = mine ? __builtin_amdgcn_readlane(cb.y, u) : fifo_co1;
+    fifo_oo0 = mine ? __builtin_amdgcn_readlane(cb.z, u) : fifo_oo0;
+    fifo_oo1 = mine ? __builtin_amdgcn_readlane(cb.w, u) : fifo_oo1;
+    ++fw;
+  };
+  auto next_entry = [&]() {
+    ++ei;
+    if (ei >= E1) {
+      fok = false;
+      return;
+    }
+    if (ei - eb == 64) {
+      eb += 64;
+      ca = na;
+      cb = nb;
+      settle(ca);
+      settle(cb);
+      load_entries(eb + 64, na, nb);
+    }
+    take_entry();
+  };
+  take_entry();
+
+  // ---- slots: product X lives in slot X % D from its fetch to its stage write.
+  // Packed word: m | n << 5 | k << 10 | valid << 15 | last << 16.
+  double sa[D][QA], sb[D][QB];
+  int32_t sw[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int j = 0; j < QA; ++j) sa[d][j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) sb[d][j] = 0.0;
+  }
+  auto fetch = [&](auto slot) {
+    constexpr int d = decltype(slot)::value;
+    int64_t ao = 0, bo = 0;
+    int32_t k = 0;
+    if (fok && frem > 0) {
+      const int u = qi - qb;
+      const int32_t dy = __builtin_amdgcn_readlane(cd.y, u);
+      ao = make64(__builtin_amdgcn_readlane(cd.x, u), dy & 0xffffff);
+      k = (int32_t)((uint32_t)dy >> 24);
+      bo = make64(__builtin_amdgcn_readlane(cd.z, u), __builtin_amdgcn_readlane(cd.w, u));
+      --frem;
+      ++qi;
+      if (qi - qb == 64) {
+        qb += 64;
+        cd = nd;
+        settle(cd);
+        load_desc(qb + 64, nd);
+      }
+    }
+    sw[d] = fm | (fn << 5) | (k << 10) | ((int32_t)fok << 15) | ((int32_t)(frem == 0) << 16);
+    const int32_t mk = fm * k, kn = k * fn;  // before the cursor moves to the next C block
+    if (fok && frem == 0) next_entry();
+    const double* pa = P.Av + ao + lane;
+    const double* pb = P.Bv + bo + lane;
+#pragma unroll
+    for (int j = 0; j < QA; ++j)
+      if (lane + 64 * j < mk) sa[d][j] = pa[64 * j];
+#pragma unroll
+    for (int j = 0; j < QB; ++j)
+      if (lane + 64 * j < kn) sb[d][j] = pb[64 * j];
+  };
+
+  // the product in the stage: its packed word
+  int32_t stw = 0;
+  auto stage_write = [&](auto slot) {
+    constexpr int d = decltype(slot)::value;
+    stw = sw[d];
+    const int32_t m = stw & 31, n = (stw >> 5) & 31, k = (stw >> 10) & 31;
+    if (k == 0) return;
+    const int32_t kpad = (k + 7) & ~7;
+    // element e of A (row-major m x k) is (e / k, e % k), of B (k x n) is
+    // (e / n, e % n): for e < 256 and divisors up to 16 the quotient is
+    // (e * ceil(2^16 / x)) >> 16 exactly
+    const uint32_t ik = kInv16[k], in = kInv16[n];
+    const int32_t mk = m * k, kn = k * n;
+#pragma unroll
+    for (int j = 0; j < QA; ++j) {
+      const int32_t e = lane + 64 * j;
+      if (e < mk) {
+        const int32_t r = (int32_t)(((uint32_t)e * ik) >> 16);
+        As[r * kMmaS + (e - r * k)] = sa[d][j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      const int32_t e = lane + 64 * j;
+      if (e < kn) {
+        const int32_t t = (int32_t)(((uint32_t)e * in) >> 16);
+        Bs[(e - t * n) * kMmaS + t] = sb[d][j];
+      }
+    }
+    // zero pads k .. kpad-1 of every A row and every B^T row (at most 7 each)
+#pragma unroll
+    for (int j = 0; j < (MP * 8 + 63) / 64; ++j) {
+      const int32_t q = lane + 64 * j, r = q >> 3, t = k + (q & 7);
+      if (r < MP && t < kpad) As[r * kMmaS + t] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < (NP * 8 + 63) / 64; ++j) {
+      const int32_t q = lane + 64 * j, c = q >> 3, t = k + (q & 7);
+      if (c < NP && t < kpad) Bs[c * kMmaS + t] = 0.0;
+    }
+  };
+
+  double acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = 0.0;
+  auto compute = [&]() {
+    const int32_t k = (stw >> 10) & 31;
+    const int32_t npair = (k + 7) >> 3;  // 0, 1 or 2
+    // the B tile column of a lane is the same in every group (4g + b mod TN = b mod TN)
+    const double* const bp = Bs + (4 * (bq % TN) + iq) * kMmaS + 2 * kk;
+    for (int32_t kp = 0; kp < npair; ++kp) {
+      const double2 bv = *reinterpret_cast<const double2*>(bp + 8 * kp);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int bi = (4 * g + bq) / TN;
+        const double2 av = *reinterpret_cast<const double2*>(As + (4 * bi + iq) * kMmaS + 8 * kp + 2 * kk);
+        acc[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av.x, bv.x, acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av.y, bv.y, acc[g], 0, 0, 0);
+      }
+    }
+  };
+
+  // Finish the C block of the product just multiplied: item g of lane
+  // 16i + 4b + j is C(4 bi + i, 4 bj + j) of tile 4g + b.
+  auto finish = [&]() {
+    const int r = fr & 63;
+    ++fr;
+    const int32_t mn = __builtin_amdgcn_readlane(fifo_mn, r);
+    const int32_t m = mn & 255, n = mn >> 8;
+    const int64_t coff = make64(__builtin_amdgcn_readlane(fifo_co0, r), __builtin_amdgcn_readlane(fifo_co1, r));
+    const int64_t oo = make64(__builtin_amdgcn_readlane(fifo_oo0, r), __builtin_amdgcn_readlane(fifo_oo1, r));
+    double* const out = P.Cv + coff;
+    const double* const ov = P.Ov + (oo >= 0 ? oo : 0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int tau = 4 * g + bq;
+      const int R = 4 * (tau / TN) + kk, Cc = 4 * (tau % TN) + iq;
+      if (R < m && Cc < n) {
+        double v = P.alpha * acc[g];
+        if (oo >= 0) v += P.beta * ov[R * n + Cc];
+        out[R * n + Cc] = v;
+      }
+      acc[g] = 0.0;
+    }
+  };
+
+  // Prime: slots 0..D-1.  Step i (slot i mod D): write the slot into the
+  // stage, refill it with product i+D, multiply; finish the C block if the
+  // product ends it.
+  static_for<0, D>([&](auto d) { fetch(d); });
+  bool more = true;
+  while (more) {
+    static_for<0, D>([&](auto idx) {
+      if (!more) return;
+      if (!((sw[decltype(idx)::value] >> 15) & 1)) {
+        more = false;
+        return;
+      }
+      wave_sync();
+      stage_write(idx);
+      fetch(idx);
+      wave_sync();
+      compute();
+      if ((stw >> 16) & 1) finish();
+    });
+  }
+}
+
+// The same launch with every class in the matrix-core form, D products in flight.
+template <int D>
+__global__ __launch_bounds__(256, 4) void k_numeric_small_mma(const double* __restrict__ Av,
+                                                            const double* __restrict__ Bv,
+                                                            const double* __restrict__ Ov,
+                                                            const int4* __restrict__ list,
+                                                            const int32_t* __restrict__ cls_start,
+                                                            const int64_t* __restrict__ qstart,
+                                                            const int4* __restrict__ desc, double* __restrict__ Cv,
+                                                            double alpha, double beta, int32_t mask) {
+  __shared__ __align__(16) double lds[4][2 * kStage];
+  const SmallOps P{Av, Bv, Ov, list, qstart, desc, Cv, alpha, beta};
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t xcd = blockIdx.x % kXcds;
+  const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
+  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
+  double* wl = &lds[wv][0];
+  for (int x = lane; x < 2 * kStage; x += 64) wl[x] = 0.0;  // stale rows stay finite
+  wave_sync();
+  int32_t b[5];
+#pragma unroll
+  for (int x = 0; x < 5; ++x) b[x] = cls_start[x];
+  if (mask & 1) small_mfma<8, 8, D>(P, wl, b[0], b[1], xcd, wpx, wix, lane);
+  if (mask & 2) small_mfma<8, 16, D>(P, wl, b[1], b[2], xcd, wpx, wix, lane);
+  if (mask & 4) small_mfma<16, 8, D>(P, wl, b[2], b[3], xcd, wpx, wix, lane);
+  if (mask & 8) small_mfma<16, 16, D>(P, wl, b[3], b[4], xcd, wpx, wix, lane);
+}
+
 // One persistent launch over every class: each wave runs its share of the
 // classes selected by `mask` (bit c = class c) in turn.  D0, D1, D2 are the
 // products in flight of the 8x8, 8x16 and 16x8 classes (16x16 always holds 2:
@@ -962,9 +1242,11 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
 using SmallKernel = void (*)(const double*, const double*, const double*, const int4*, const int32_t*,
                             const int64_t*, const int4*, double*, double, double, int32_t);
 constexpr SmallKernel kSmallKernels[] = {k_numeric_small<1, 1, 1>, k_numeric_small<1, 2, 2>, k_numeric_small<4, 2, 2>,
-                                         k_numeric_small<1, 1, 2>, k_numeric_small<1, 2, 1>, k_numeric_small<8, 2, 2>};
+                                         k_numeric_small<1, 1, 2>, k_numeric_small<1, 2, 1>, k_numeric_small<8, 2, 2>,
+                                         k_numeric_small_mma<2>,   k_numeric_small_mma<3>};
 
-constexpr int kSmallDepths[][4] = {{1, 1, 1, 2}, {1, 2, 2, 2}, {4, 2, 2, 2}, {1, 1, 2, 2}, {1, 2, 1, 2}, {8, 2, 2, 2}};
+constexpr int kSmallDepths[][4] = {{1, 1, 1, 2}, {1, 2, 2, 2}, {4, 2, 2, 2}, {1, 1, 2, 2},
+                                   {1, 2, 1, 2}, {8, 2, 2, 2}, {18, 18, 18, 18}, {19, 19, 19, 19}};
 static_assert(sizeof(kSmallKernels) / sizeof(kSmallKernels[0]) == kSmallVariants, "variant table");
 static_assert(sizeof(kSmallDepths) / sizeof(kSmallDepths[0]) == kSmallVariants, "variant table");
 

@@ -1,17 +1,21 @@
 """Autotuner of the small-block path and its table.
 
 The small-block kernel pads every block to one of four shape classes
-(8 or 16 rows by 8 or 16 columns) and runs all classes in one persistent
-launch; a pipeline variant fixes how many block products each wave keeps in
-flight per class.  Section 2 of the paper tunes the batched multiply for each
-set of block dimensions; here the tuner times every variant on each class of
-a real product (bsmm_tune_small) and keeps the fastest in a table keyed by the
-block edges of A's rows, A's columns and B's columns.
+(8 or 16 rows by 8 or 16 columns); a variant fixes per class the form of the
+block product (FP64 vector units or FP64 matrix cores) and how many block
+products each wave keeps in flight.  Section 2 of the paper tunes the batched
+multiply for each set of block dimensions; here the tuner times every variant
+on each class of a real product (bsmm_tune_small) and keeps, per class, the
+fastest in a table keyed by the block edges of A's rows, A's columns and B's
+columns; the classes then run each with its own variant.
 
 The table is saved as JSON, one entry per edge set:
 
     {"arch": "gfx950", "entries": [{"rows": [5, 13], "inner": [5, 13],
-      "cols": [5, 13], "variant": 1, "depths": [4, 2, 2, 2], "ms": [...]}]}
+      "cols": [5, 13], "variants": [6, 6, 6, 7], "depths": [18, 18, 18, 19],
+      "ms": [...]}]}
+
+(`depths[c]` is bsmm_small_variant(variants[c])[c].)
 
 `load()` enters a saved table into the library; the package loads
 tune_gfx950.json next to this file, if present, when the library is first
@@ -51,11 +55,12 @@ def tune(alpha, A, B, beta, C_in, C_out, eps, reps=5, stream=None):
     Returns the table entry (None if the small-block path does not serve it)."""
     v, ms = bsmm.bsmm_tune_small(alpha, A.handle, B.handle, beta, C_in.handle if C_in is not None else None,
                                  C_out.handle, eps, reps, stream)
-    if v < 0:
+    if v[0] < 0:
         return None
     rows, inner, cols = key_edges(bsmm.bsmm_tune_key(A.handle, B.handle))
-    return {"rows": rows, "inner": inner, "cols": cols, "variant": int(v),
-            "depths": bsmm.bsmm_small_variant(v), "ms": [[round(x / reps, 5) for x in r] for r in ms.tolist()]}
+    return {"rows": rows, "inner": inner, "cols": cols, "variants": [int(x) for x in v],
+            "depths": [bsmm.bsmm_small_variant(x)[c] for c, x in enumerate(v)],
+            "ms": [[round(x / reps, 5) for x in r] for r in ms.tolist()]}
 
 
 def load(path=TABLE):
@@ -64,7 +69,7 @@ def load(path=TABLE):
         table = json.load(f)
     entries = table.get("entries", [])
     for e in entries:
-        bsmm.bsmm_tune_set(edges_key(e["rows"], e["inner"], e["cols"]), int(e["variant"]))
+        bsmm.bsmm_tune_set(edges_key(e["rows"], e["inner"], e["cols"]), [int(x) for x in e["variants"]])
     return entries
 
 

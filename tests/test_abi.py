@@ -62,7 +62,9 @@ def test_tuning_table_without_device():
     assert len(set(map(tuple, depths))) == bsmm.BSMM_SMALL_VARIANTS
     assert depths[1] == [1, 2, 2, 2]  # the untuned choice
     for d in depths:
-        assert d[0] in (1, 4, 8) and d[1] in (1, 2, 4) and d[2] in (1, 2, 4) and d[3] == 2
+        # vector-unit forms, or the matrix-core form (16 + products in flight) in every class
+        assert (d[0] in (1, 4, 8) and d[1] in (1, 2, 4) and d[2] in (1, 2, 4) and d[3] == 2) or \
+            (d[0] > 16 and d == [d[0]] * 4)
     with pytest.raises(bsmm.BsmmError):
         bsmm.bsmm_small_variant(bsmm.BSMM_SMALL_VARIANTS)
     key = tune.edges_key([5, 13], [13], [1, 16])
@@ -72,14 +74,16 @@ def test_tuning_table_without_device():
         tune.edges_key([17], [1], [1])
     saved = bsmm.bsmm_tune_entries()
     try:
-        bsmm.bsmm_tune_set(key, 3)
-        assert bsmm.bsmm_tune_get(key) == 3
-        assert bsmm.bsmm_tune_entries()[key] == 3
-        bsmm.bsmm_tune_set(key, -1)
-        assert bsmm.bsmm_tune_get(key) == -1 and key not in bsmm.bsmm_tune_entries()
-        with pytest.raises(bsmm.BsmmError) as e:
-            bsmm.bsmm_tune_set(key, bsmm.BSMM_SMALL_VARIANTS)
-        assert e.value.status == "BSMM_E_ARG"
+        bsmm.bsmm_tune_set(key, [3, 6, 0, 7])
+        assert bsmm.bsmm_tune_get(key) == [3, 6, 0, 7]
+        assert bsmm.bsmm_tune_entries()[key] == [3, 6, 0, 7]
+        bsmm.bsmm_tune_set(key, None)
+        assert bsmm.bsmm_tune_get(key) == [-1] * 4 and key not in bsmm.bsmm_tune_entries()
+        for bad in ([0, 0, 0, bsmm.BSMM_SMALL_VARIANTS], [-1, 0, 0, 0]):
+            with pytest.raises(bsmm.BsmmError) as e:
+                bsmm.bsmm_tune_set(key, bad)
+            assert e.value.status == "BSMM_E_ARG"
+        assert key not in bsmm.bsmm_tune_entries()
     finally:
         assert bsmm.bsmm_tune_entries() == saved
 
@@ -93,26 +97,26 @@ def test_saved_tuning_table():
     table = json.load(open(tune.TABLE))
     assert table["arch"] == "gfx950"
     for e in table["entries"]:
-        assert 0 <= e["variant"] < bsmm.BSMM_SMALL_VARIANTS
-        assert e["depths"] == bsmm.bsmm_small_variant(e["variant"])
-        assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variant"]
+        assert all(0 <= v < bsmm.BSMM_SMALL_VARIANTS for v in e["variants"]) and len(e["variants"]) == 4
+        assert e["depths"] == [bsmm.bsmm_small_variant(v)[c] for c, v in enumerate(e["variants"])]
+        assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variants"]
 
 
 def test_tuning_table_json_roundtrip(tmp_path):
     from paper_1708_03604_amd import tune
     bsmm.lib()
     saved = bsmm.bsmm_tune_entries()
-    entries = [{"rows": [5, 13], "inner": [5, 13], "cols": [5, 13], "variant": 3, "depths": bsmm.bsmm_small_variant(3)},
-               {"rows": [2], "inner": [7, 8], "cols": [1, 16], "variant": 0, "depths": bsmm.bsmm_small_variant(0)}]
+    entries = [{"rows": [5, 13], "inner": [5, 13], "cols": [5, 13], "variants": [3, 6, 6, 7], "depths": [1, 18, 18, 19]},
+               {"rows": [2], "inner": [7, 8], "cols": [1, 16], "variants": [0, 0, 0, 0], "depths": [1, 1, 1, 2]}]
     path = str(tmp_path / "table.json")
     try:
         tune.save(entries, path, note="test")
         loaded = tune.load(path)
         assert loaded == entries
         for e in entries:
-            assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variant"]
+            assert bsmm.bsmm_tune_get(tune.edges_key(e["rows"], e["inner"], e["cols"])) == e["variants"]
     finally:
         for k in bsmm.bsmm_tune_entries():
-            bsmm.bsmm_tune_set(k, -1)
+            bsmm.bsmm_tune_set(k, None)
         for k, v in saved.items():
             bsmm.bsmm_tune_set(k, v)

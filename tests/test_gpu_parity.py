@@ -73,6 +73,9 @@ SIZE_SETS = {
     "b32": ([32] * 10, [32] * 10, [32] * 10),
     # every class boundary of the small-block path: edges 1, 8, 9, 15, 16
     "edge16": ([16, 9, 8, 1, 15] * 5, [16, 8, 3, 16, 9] * 6, [9, 16, 8, 2] * 6),
+    # every edge >= 16, not uniform: the generic path's matrix-core form, with
+    # partial 32x32 sub-tiles, K chunks past 32 and inner sizes not a multiple of 8
+    "wide": ([16, 40, 33, 64, 17] * 2, [24, 48, 16, 31, 65] * 2, [20, 65, 32, 16] * 3),
 }
 
 

@@ -1,7 +1,8 @@
 """Randomised parity over every kernel path, through the C-ABI.
 
 Each case draws block sizes (from the sets that select the small-block,
-23x23, tiled and split paths), densities, alpha, beta and the filter
+23x23, generic and split paths; the "wide" set, every edge at least 16, sends
+the generic path's blocks to its matrix-core form), densities, alpha, beta and the filter
 threshold from its seed, runs the multiply synchronously and with reserved
 capacities, and compares both with the oracle: pattern and stack bit-exact,
 FP64 values within 1e-12 relative Frobenius (split precision: within its
@@ -22,6 +23,7 @@ SIZE_SETS = {
     "b23": [23],
     "mixed": [4, 9, 17, 22, 23, 32, 40],
     "b5_13": [5, 13],
+    "wide": [16, 17, 24, 31, 32, 33, 40, 48, 64],
 }
 
 
@@ -68,7 +70,7 @@ def run(A, B, Co, alpha, beta, eps, prec, reserve):
     return out
 
 
-@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("seed", range(30))
 def test_random_case(seed):
     name, A, B, Co, alpha, beta, eps = draw(seed)
     ref = oracle.multiply(alpha, A, B, beta, Co if beta != 0.0 else None, eps)
