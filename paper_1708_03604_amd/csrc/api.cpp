@@ -618,7 +618,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // allocates or synchronises (graph-capturable); the bounds are capacities.
   const bool reserved = C->cap_nnzb > 0;
   // scratch
-  if (C->flags.ensure(2) != hipSuccess || C->work.ensure(1) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
+  if (C->flags.ensure(2) != hipSuccess || C->work.ensure(numeric_work_elems()) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
@@ -786,14 +786,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   if (split) {
     HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
     HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
-    HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, s));
+    HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, C->work.p, s));
   } else if (slice) {
     HIP_W(launch_slice_int8x7(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, A->cur.row_ptr.p, A->nbrows, nullptr,
                                 A->nbrows, C->slice_rowof.p, C->slice_ea.p, C->slice_a.p, s));
     HIP_W(launch_slice_int8x7(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, nullptr, 0, B->cur.col_idx.p, B->nbcols,
                                 nullptr, C->slice_eb.p, C->slice_b.p, s));
     HIP_W(launch_numeric_slice23(na, out.row_ptr.p, nbrows, C->slice_a.p, C->slice_b.p, C->slice_ea.p,
-                                   C->slice_eb.p, s));
+                                   C->slice_eb.p, C->work.p, s));
   } else if (small) {
     HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
                                C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
@@ -997,7 +997,7 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
               m->class_start.ensure(5) == hipSuccess && m->class_np.ensure(nce) == hipSuccess &&
               m->class_q.ensure(nce + 1) == hipSuccess)) &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
-            m->flags.ensure(2) == hipSuccess && m->work.ensure(1) == hipSuccess &&
+            m->flags.ensure(2) == hipSuccess && m->work.ensure(numeric_work_elems()) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&
             m->norm_self.ensure(cb) == hipSuccess && m->fkeep.ensure(cb + 1) == hipSuccess &&
             m->fvsz.ensure(cb + 1) == hipSuccess && m->fpos.ensure(cb + 1) == hipSuccess &&

@@ -140,6 +140,13 @@ hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64
 hipError_t launch_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
                                 const int64_t* cand_pre, const int64_t* nf_pre, const uint32_t* flags,
                                 int64_t* totals, hipStream_t s);
+// `work` holds numeric_work_elems() entries (the 23x23 kernels' schedule).
+int64_t numeric_work_elems();
+// Schedule of the 23x23 kernels (FP64, split, exact slices): slices of equal
+// product counts per XCD part into `work`; returns the slices per part.  The
+// kernels run on tile23_workgroups() workgroups of four waves.
+int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, int32_t* work, hipStream_t s);
+int32_t tile23_workgroups();
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s);
 
 // Small-block path (every block edge <= kSmallEdge): C blocks are partitioned
@@ -178,7 +185,8 @@ hipError_t launch_numeric_small(const NumArgs& a, const int4* list, const int32_
 int64_t split_elems(int64_t nblocks);
 hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int64_t bound, int transpose,
                                uint16_t* out, hipStream_t s);
-hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, hipStream_t s);
+hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, int32_t* work,
+                                  hipStream_t s);
 
 // Exact-slice precision (23x23 blocks): seven INT8 digits per value under a
 // power-of-two scale per row of each block row of A (transpose = 0, scale
@@ -190,7 +198,8 @@ hipError_t launch_slice_int8x7(const double* values, const int64_t* d_nnzb, int6
                                const int32_t* row_ptr, int32_t nbrows, const int32_t* col_idx, int32_t ngroups,
                                int32_t* rowof, int32_t* exps, uint8_t* out, hipStream_t s);
 hipError_t launch_numeric_slice23(const NumArgs& a, const int32_t* c_row_ptr, int32_t nbrows, const uint8_t* As,
-                                  const uint8_t* Bs, const int32_t* ea, const int32_t* eb, hipStream_t s);
+                                  const uint8_t* Bs, const int32_t* ea, const int32_t* eb, int32_t* work,
+                                  hipStream_t s);
 
 // filter(M, eps) over the first dsz[0] blocks (bound >= dsz[0] sizes the
 // launches; keep/vsz/keep_pos/voff are scratch of bound (+1) entries).  The

@@ -248,11 +248,37 @@ constexpr int kTileEdge = 24;
 __device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_t n, int64_t t) {
   int32_t lo = 0, hi = n;
   while (lo < hi) {
-    const int32_t mid = __builtin_amdgcn_readfirstlane((lo + hi) >> 1);
+    const int32_t mid = (lo + hi) >> 1;
     if (prod_ptr[mid] < t) lo = mid + 1;
     else hi = mid;
   }
   return lo;
+}
+
+// Schedule of the 23x23 kernel: the C blocks are cut into 8 XCD parts of
+// equal product counts (XCD x: products [P x / 8, P (x+1) / 8)), and each
+// part into ns slices of equal product counts, cut at C block boundaries:
+// bounds[x (ns+1) + j] is the first C block of slice j of part x.  Waves
+// take every wpx-th slice of their XCD's part, so each wave gets about the
+// same number of products while an XCD still works on nearby block rows.
+constexpr int kKernelXcds = 8;
+constexpr int kSlicesPerWave = 32;
+__global__ void k_product_slices(const int64_t* __restrict__ prod_ptr, const int64_t* __restrict__ totals, int32_t ns,
+                                 int32_t* __restrict__ bounds) {
+  const int32_t nnzc = live_nnzc(totals);
+  const int64_t P = prod_ptr[nnzc];
+  const int32_t per = ns + 1;
+  for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < kKernelXcds * per; t += gridDim.x * 256) {
+    const int32_t x = t / per, j = t - x * per;
+    const int64_t p0 = P * x / kKernelXcds, p1 = P * (x + 1) / kKernelXcds;
+    const int32_t X0 = lower_bound_c(prod_ptr, nnzc, p0);
+    const int32_t X1 = x == kKernelXcds - 1 ? nnzc : lower_bound_c(prod_ptr, nnzc, p1);
+    int32_t b;
+    if (j == 0) b = X0;
+    else if (j == ns) b = X1;
+    else b = min(X1, max(X0, lower_bound_c(prod_ptr, nnzc, p0 + (p1 - p0) * j / ns)));
+    bounds[t] = b;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -260,9 +286,10 @@ __device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_
 // (v_mfma_f64_4x4x4_4b: four independent 4x4x4 products per instruction, which
 // pad a 23-edge only to 24).  One wave per C block at a time; the product
 // stack is one flat array ordered by C block: each XCD (workgroup b runs on
-// XCD b mod 8) owns a contiguous run of C blocks with 1/8 of the products, its
-// waves take interleaved chunks of two C blocks and walk their products as one
-// stream (operands of the next product in registers, two LDS stages).
+// XCD b mod 8) owns a contiguous run of C blocks with 1/8 of the products, cut
+// into slices of equal product counts (k_product_slices); its waves take every
+// wpx-th slice and walk their products as one stream (operands of the next
+// product in registers, two LDS stages).
 //
 // Instruction layout (measured on the device): lane 16k + 4b + i holds
 // A_b[i][k] and B_b[k][i'] with i' = i, and the result lane 16i + 4b + j holds
@@ -283,7 +310,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
     const double* __restrict__ Av, const double* __restrict__ Bv, const double* __restrict__ Ov,
     const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
     const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals, int use_old,
-    double alpha, double beta) {
+    double alpha, double beta, const int32_t* __restrict__ bounds, int32_t ns) {
   static_assert(S >= 17 && S <= kTileEdge, "matrix-core kernel covers edges 17..24");
   constexpr int NE = S * S;
   constexpr int PER = (NE + 63) / 64;
@@ -310,31 +337,26 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   const int afrag = (4 * (fb >> 1) + fi) * kMfmaStride + 2 * fk;
   const int bfrag = kMfmaOperand + (4 * (fb & 1) + fi) * kMfmaStride + 2 * fk;
 
-  constexpr int kXcds = 8;
-  constexpr int kChunk = 2;
-  const int32_t xcd = blockIdx.x % kXcds;
-  const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;  // waves per XCD
-  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
+  const int32_t xcd = blockIdx.x % kKernelXcds;
+  const int32_t wpx = (int32_t)(gridDim.x / kKernelXcds) * 4;  // waves per XCD
+  const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kKernelXcds) * 4 + wv);
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
-  const int64_t P = prod_ptr[nnzc];
-  const int32_t X0 = lower_bound_c(prod_ptr, nnzc, P * xcd / kXcds);
-  const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_c(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
+  const int32_t* const bnd = bounds + xcd * (ns + 1);
 
+  // fetch cursor: slice iq, products [ip, ip_end)
   int32_t iq = wix;
   int64_t ip = 0, ip_end = 0;
-  if (X0 + (int64_t)iq * kChunk < X1) {
-    const int32_t c0 = X0 + iq * kChunk;
-    ip = prod_ptr[c0];
-    ip_end = prod_ptr[min(c0 + kChunk, X1)];
+  if (iq < ns) {
+    ip = prod_ptr[bnd[iq]];
+    ip_end = prod_ptr[bnd[iq + 1]];
   }
   auto next_index = [&]() -> int64_t {
     while (ip >= ip_end) {
       iq += wpx;
-      if (X0 + (int64_t)iq * kChunk >= X1) return -1;
-      const int32_t c0 = X0 + iq * kChunk;
-      ip = prod_ptr[c0];
-      ip_end = prod_ptr[min(c0 + kChunk, X1)];
+      if (iq >= ns) return -1;
+      ip = prod_ptr[bnd[iq]];
+      ip_end = prod_ptr[bnd[iq + 1]];
     }
     return ip++;
   };
@@ -416,12 +438,14 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
     }
   };
 
+  // compute cursor: slice cq, C blocks [c, c1), products [p, pe) of block c
   int32_t cq = wix;
   int32_t c = 0, c1 = 0;
   int64_t p = 0, pe = 0;
-  if (X0 + (int64_t)cq * kChunk >= X1) return;
-  c = X0 + cq * kChunk;
-  c1 = min(c + kChunk, X1);
+  while (cq < ns && bnd[cq] == bnd[cq + 1]) cq += wpx;
+  if (cq >= ns) return;
+  c = bnd[cq];
+  c1 = bnd[cq + 1];
   p = prod_ptr[c];
   pe = prod_ptr[c + 1];
 #pragma unroll
@@ -482,10 +506,12 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
         for (int J = 0; J < 3; ++J) acc[I][J] = 0.0;
       ++c;
       if (c == c1) {
-        cq += wpx;
-        if (X0 + (int64_t)cq * kChunk >= X1) return false;
-        c = X0 + cq * kChunk;
-        c1 = min(c + kChunk, X1);
+        do {
+          cq += wpx;
+          if (cq >= ns) return false;
+        } while (bnd[cq] == bnd[cq + 1]);
+        c = bnd[cq];
+        c1 = bnd[cq + 1];
         p = prod_ptr[c];
       }
       pe = prod_ptr[c + 1];
@@ -503,17 +529,35 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   }
 }
 
+// Grid of the 23x23 kernel: two workgroups of 4 waves per CU, a multiple of 8 (XCDs).
+static int32_t tile23_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return ((cus * 2 + kKernelXcds - 1) / kKernelXcds) * kKernelXcds;
+}
+
+int64_t numeric_work_elems() {
+  const int64_t ns = (int64_t)tile23_grid() / kKernelXcds * 4 * kSlicesPerWave;
+  return kKernelXcds * (ns + 1);
+}
+
+int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, int32_t* work, hipStream_t s) {
+  const int32_t ns = tile23_grid() / kKernelXcds * 4 * kSlicesPerWave;
+  const int32_t n = kKernelXcds * (ns + 1);
+  hipLaunchKernelGGL(k_product_slices, dim3((n + 255) / 256), dim3(256), 0, s, prod_ptr, totals, ns, work);
+  return ns;
+}
+
+int32_t tile23_workgroups() { return tile23_grid(); }
+
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
-  (void)work;
   if (uniform_size == 23) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int32_t blocks = cus * 2;   // two workgroups of 4 waves per CU, a multiple of 8 (XCDs)
-    blocks = ((blocks + 7) / 8) * 8;
+    const int32_t blocks = tile23_grid();
+    const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, work, s);
     hipLaunchKernelGGL(k_numeric_mfma24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
                        a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
-                       a.c_values, a.totals, a.use_old, a.alpha, a.beta);
+                       a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);
     return hipGetLastError();
   }
   int dev = 0, cus = 256;

@@ -73,16 +73,6 @@ __global__ __launch_bounds__(256) void k_split_bf16x3(const double* __restrict__
 }
 
 
-__device__ __forceinline__ int32_t lower_bound_cs(const int64_t* prod_ptr, int32_t n, int64_t t) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = __builtin_amdgcn_readfirstlane((lo + hi) >> 1);
-    if (prod_ptr[mid] < t) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -90,15 +80,15 @@ __device__ __forceinline__ void wsync() {
 }
 
 // Schedule as in the FP64 23x23 kernel: each XCD owns a contiguous run of C
-// blocks holding 1/8 of the products; its waves take interleaved chunks of
-// kChunk consecutive C blocks.  Products are fetched two steps ahead into two
-// register slots; one LDS stage per wave, written after the previous product
-// has been read.
+// blocks holding 1/8 of the products, cut into slices of equal product
+// counts (launch_product_slices); its waves take every wpx-th slice.
+// Products are fetched two steps ahead into two register slots; one LDS
+// stage per wave, written after the previous product has been read.
 __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     const uint16_t* __restrict__ As, const uint16_t* __restrict__ Bs, const double* __restrict__ Ov,
     const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
     const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals,
-    int use_old, double alpha, double beta) {
+    int use_old, double alpha, double beta, const int32_t* __restrict__ bounds, int32_t ns) {
   constexpr int NE = kE * kE;
   constexpr int PER_C = (NE + 63) / 64;
   constexpr int LAST_C = NE - 64 * (PER_C - 1);
@@ -121,28 +111,25 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
 
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
-  constexpr int kXcds = 8, kChunk = 2;
+  constexpr int kXcds = 8;
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
-  const int64_t P = prod_ptr[nnzc];
-  const int32_t X0 = lower_bound_cs(prod_ptr, nnzc, P * xcd / kXcds);
-  const int32_t X1 = (xcd == kXcds - 1) ? nnzc : lower_bound_cs(prod_ptr, nnzc, P * (xcd + 1) / kXcds);
+  const int32_t* const bnd = bounds + xcd * (ns + 1);
 
+  // fetch cursor: slice iq of the XCD's part, products [ip, ip_end)
   int32_t iq = wix;
   int64_t ip = 0, ip_end = 0;
-  if (X0 + (int64_t)iq * kChunk < X1) {
-    const int32_t c0 = X0 + iq * kChunk;
-    ip = prod_ptr[c0];
-    ip_end = prod_ptr[min(c0 + kChunk, X1)];
+  if (iq < ns) {
+    ip = prod_ptr[bnd[iq]];
+    ip_end = prod_ptr[bnd[iq + 1]];
   }
   auto next_index = [&]() -> int64_t {
     while (ip >= ip_end) {
       iq += wpx;
-      if (X0 + (int64_t)iq * kChunk >= X1) return -1;
-      const int32_t c0 = X0 + iq * kChunk;
-      ip = prod_ptr[c0];
-      ip_end = prod_ptr[min(c0 + kChunk, X1)];
+      if (iq >= ns) return -1;
+      ip = prod_ptr[bnd[iq]];
+      ip_end = prod_ptr[bnd[iq + 1]];
     }
     return ip++;
   };
@@ -221,11 +208,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
       }
   };
 
+  // compute cursor: slice cq, C blocks [c, c1), products [p, pe) of block c
   int32_t cq = wix, c = 0, c1 = 0;
   int64_t p = 0, pe = 0;
-  if (X0 + (int64_t)cq * kChunk >= X1) return;
-  c = X0 + cq * kChunk;
-  c1 = min(c + kChunk, X1);
+  while (cq < ns && bnd[cq] == bnd[cq + 1]) cq += wpx;
+  if (cq >= ns) return;
+  c = bnd[cq];
+  c1 = bnd[cq + 1];
   p = prod_ptr[c];
   pe = prod_ptr[c + 1];
 #pragma unroll
@@ -273,10 +262,12 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
       for (int x = 0; x < 16; ++x) acc[x] = 0.0;
       ++c;
       if (c == c1) {
-        cq += wpx;
-        if (X0 + (int64_t)cq * kChunk >= X1) return false;
-        c = X0 + cq * kChunk;
-        c1 = min(c + kChunk, X1);
+        do {
+          cq += wpx;
+          if (cq >= ns) return false;
+        } while (bnd[cq] == bnd[cq + 1]);
+        c = bnd[cq];
+        c1 = bnd[cq + 1];
         p = prod_ptr[c];
       }
       pe = prod_ptr[c + 1];
@@ -325,14 +316,13 @@ hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int6
   return hipGetLastError();
 }
 
-hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, hipStream_t s) {
+hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const uint16_t* Bs, int32_t* work,
+                                  hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  int32_t blocks = ((cus * 2 + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_numeric_split23, dim3(blocks), dim3(256), 0, s, As, Bs,
+  const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, work, s);
+  hipLaunchKernelGGL(k_numeric_split23, dim3(tile23_workgroups()), dim3(256), 0, s, As, Bs,
                      a.use_old ? a.Cin.values : a.c_values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
-                     a.c_values, a.totals, a.use_old, a.alpha, a.beta);
+                     a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);
   return hipGetLastError();
 }
 
