@@ -262,7 +262,7 @@ __device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_
 // take every wpx-th slice of their XCD's part, so each wave gets about the
 // same number of products while an XCD still works on nearby block rows.
 constexpr int kKernelXcds = 8;
-constexpr int kSlicesPerWave = 32;
+constexpr int kSlicesPerWave = 16;  // measured: 8 1.63 ms, 16 1.60, 32 1.65, 64 1.76 (molecules)
 __global__ void k_product_slices(const int64_t* __restrict__ prod_ptr, const int64_t* __restrict__ totals, int32_t ns,
                                  int32_t* __restrict__ bounds) {
   const int32_t nnzc = live_nnzc(totals);
