@@ -97,6 +97,7 @@ typedef struct {
   int32_t path;        /* BSMM_PATH_* */
   int32_t variants[4]; /* small-block variant used per shape class 8x8, 8x16, 16x8, 16x16
                           (-1 on other paths) */
+  int32_t panels;      /* stack panels the products were built and consumed in (1: whole stack) */
 } bsmm_mult_stats;
 
 /*
@@ -133,7 +134,10 @@ bsmm_status bsmm_destroy(bsmm_mat m);
  *     (BSMM_E_SHAPE).
  *   - alpha, beta and filter_eps must be finite (BSMM_E_ARG).
  *   - Synchronises `stream` once, after the symbolic phase, to size C_out,
- *     unless C_out is reserved (bsmm_reserve): then it never synchronises.
+ *     unless C_out is reserved (bsmm_reserve): then it never synchronises
+ *     (twice when the stack is built in panels, see bsmm_set_stack_limit).
+ *   - Symbolic pass limits: at most 2048 stored blocks in a block row of A
+ *     and 2048 blocks in a block row of the result (BSMM_E_UNSUPPORTED).
  * Errors: a call rejected by its checks (arguments, shapes, aliasing, the
  * symbolic pass limits, capacity, an unsupported precision/size pair) leaves
  * C_out as it was, values, pattern and product stack included.  If device
@@ -204,6 +208,8 @@ bsmm_status bsmm_export(bsmm_mat m, int32_t* row_ptr, int32_t* col_idx, double* 
  * block product, (C block, A block, B block) indices in CSR order, sorted by
  * C block and then by the inner block index k.  *nprod receives the count;
  * the arrays (any may be NULL) must hold that many entries.  Synchronises.
+ * BSMM_E_UNSUPPORTED if that multiply built its stack in panels (see
+ * bsmm_set_stack_limit): panels are consumed and not kept.
  */
 bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t* st_b, int64_t* nprod,
                               int ptr_kind, void* stream);
@@ -287,11 +293,32 @@ bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, in
  * BSMM_E_CAPACITY (or BSMM_E_UNSUPPORTED for a row beyond the symbolic
  * limits), after which m is empty.  The current contents of m are kept.
  * Inputs of such a multiply must not hold more blocks than the capacity of
- * the output (the norm scratch of the filter is sized by it).  Synchronises
- * `stream` once.  Capacities must be >= 1 and block/product capacities below
- * 2^31.
+ * the output (the norm scratch of the filter is sized by it).  The operand
+ * buffers of split and exact-slice precision are not reserved: the first
+ * multiply into m in such a precision allocates them (run it once before
+ * capturing).  Synchronises `stream` once.  Capacities must be >= 1, the
+ * block capacity below 2^31, and the product capacity too unless m has
+ * uniform 23x23 blocks (stack panels, see bsmm_set_stack_limit).
  */
 bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_t max_products, void* stream);
+
+/*
+ * Stack limit of m (Section 2: the local multiply fills stacks of block
+ * products and processes each when it is full): the block products one
+ * stack panel of a multiply into m may hold, 2 .. 2^31-1, default 2^30 (8 GB
+ * of indices).  A multiply of uniform 23x23 blocks (any precision) with more
+ * products than the limit builds and consumes its stack in panels of
+ * consecutive C block rows, each holding at most the limit (a panel starts
+ * at every multiple of half the limit, so a block row may hold at most half
+ * of it: BSMM_E_CAPACITY otherwise).  Results are bit-identical to the
+ * whole-stack multiply.  Other block sizes build the whole stack (at most
+ * 2^31-1 products) whatever the limit.  For a reserved output the limit sizes
+ * the stack: bsmm_reserve allocates min(max_products, limit) entries and the
+ * multiplies run ceil(max_products / (limit/2)) + 1 panels (at most 4096;
+ * empty panels cost a few launches), so max_products may exceed 2^31-1 for
+ * 23x23 blocks.  Set it before bsmm_reserve (BSMM_E_ARG after).
+ */
+bsmm_status bsmm_set_stack_limit(bsmm_mat m, int64_t max_products);
 
 /*
  * ||m||_F of all stored values into out[0] (device memory owned by the

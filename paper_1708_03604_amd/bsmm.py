@@ -42,7 +42,7 @@ class BsmmError(RuntimeError):
 class MultStats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("products", ctypes.c_int64), ("nnzb", ctypes.c_int64),
                 ("nvals", ctypes.c_int64), ("useful_flops", ctypes.c_double), ("path", ctypes.c_int32),
-                ("variants", ctypes.c_int32 * 4)]
+                ("variants", ctypes.c_int32 * 4), ("panels", ctypes.c_int32)]
 
 
 # every function declared in include/bsmm.h, with its ctypes signature
@@ -63,6 +63,7 @@ SIGNATURES = {
     "bsmm_phase_times": ([_vp, _vp, _vp], _int),
     "bsmm_last_error": ([], ctypes.c_char_p),
     "bsmm_reserve": ([_vp, _i64, _i64, _i64, _vp], _int),
+    "bsmm_set_stack_limit": ([_vp, _i64], _int),
     "bsmm_frobenius": ([_vp, _vp, _vp], _int),
     "bsmm_capture_begin": ([_vp], _int),
     "bsmm_capture_end": ([_vp, _vp], _int),
@@ -224,6 +225,10 @@ def bsmm_last_error():
 def bsmm_reserve(M, max_nnzb, max_nvals, max_products, stream=None):
     _check("bsmm_reserve", lib().bsmm_reserve(M, int(max_nnzb), int(max_nvals), int(max_products),
                                               _stream(stream)))
+
+
+def bsmm_set_stack_limit(M, max_products):
+    _check("bsmm_set_stack_limit", lib().bsmm_set_stack_limit(M, int(max_products)))
 
 
 def bsmm_frobenius(M, out, stream=None):

@@ -37,10 +37,12 @@ class SignChain:
     (max blocks, max values, max products per multiply) of the reserved work
     matrices (default: dense).  `prec` is the precision of the iteration's
     multiplies (bsmm.BSMM_FP64 or bsmm.BSMM_SPLIT_BF16X3); the residual
-    multiply is FP64.
+    multiply is FP64.  `stack_limit` (optional) caps the products one stack
+    panel of the work matrices holds (bsmm_set_stack_limit): with the dense
+    default capacities the multiplies then build their stacks in panels.
     """
 
-    def __init__(self, X0, steps=12, eps=1e-7, caps=None, stream=None, prec=bsmm.BSMM_FP64):
+    def __init__(self, X0, steps=12, eps=1e-7, caps=None, stream=None, prec=bsmm.BSMM_FP64, stack_limit=None):
         import torch
         self.steps = steps
         self.eps = eps
@@ -56,6 +58,8 @@ class SignChain:
         self.T = bsmm.Matrix.empty(rs, cs, st)
         self.R = bsmm.Matrix.empty(rs, cs, st)
         for m in self.X + [self.T, self.R]:
+            if stack_limit is not None:
+                bsmm.bsmm_set_stack_limit(m.handle, stack_limit)
             bsmm.bsmm_reserve(m.handle, nnzb, nvals, nprod, st)
         self.residual = torch.zeros(1, dtype=torch.float64, device="cuda")
         self.graph = None

@@ -88,6 +88,16 @@ struct Storage {
 
 constexpr int64_t kValueSlack = kValueSlackDoubles;
 constexpr int kPinned = 16;
+// Default stack limit: 2^30 products (8 GB of stack indices); a 23x23
+// multiply with more products builds and consumes its stack in panels.
+constexpr int64_t kDefaultStackLimit = int64_t(1) << 30;
+
+// Panels for `products` block products under a stack limit (half the limit
+// per panel start, plus one: see launch_panel_rows).
+int64_t panels_for(int64_t products, int64_t limit) {
+  const int64_t half = std::max<int64_t>(limit / 2, 1);
+  return (products + half - 1) / half + 1;
+}
 
 }  // namespace
 
@@ -121,6 +131,12 @@ struct bsmm_matrix {
   DBuf<uint32_t> flags;
   DBuf<int32_t> work;
   DBuf<int32_t> wide;   // rows for the workgroup forms of the symbolic pass (count in flags[1])
+  DBuf<int32_t> huge;   // rows for the huge forms of the symbolic pass (count in flags[2])
+  DBuf<int32_t> panels; // row bounds of the stack panels (23x23 paths)
+  int64_t stack_limit = kDefaultStackLimit;  // products one stack panel may hold (23x23 paths)
+  int64_t cap_stack = 0;        // reserved: stack entries allocated
+  int32_t res_panels = 1;       // reserved: stack panels per multiply on the 23x23 paths
+  bool stack_panelled = false;  // the last multiply built its stack in panels (not kept)
   DBuf<int4> class_list;          // C blocks by padded shape class (small-block path), 2 per block
   DBuf<int4> prod_desc;           // per product operand offsets (small-block path)
   DBuf<uint16_t> split_a, split_b; // BF16 terms of the operands (split precision)
@@ -228,6 +244,7 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
     m->nvals = 0;
     m->nprod = 0;
     m->has_stack = false;
+    m->stack_panelled = false;
     m->stats = bsmm_mult_stats{};
     std::fill(m->stats.variants, m->stats.variants + 4, -1);
     const int64_t zero[3] = {0, 0, 0};
@@ -262,6 +279,7 @@ bsmm_status empty_result(bsmm_matrix* C, hipStream_t s, bsmm_status code, const 
   C->nvals = 0;
   C->nprod = 0;
   C->has_stack = false;
+  C->stack_panelled = false;
   C->stats = bsmm_mult_stats{};
   std::fill(C->stats.variants, C->stats.variants + 4, -1);
   const int64_t zero[4] = {0, 0, 0, 0};
@@ -502,6 +520,8 @@ bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t*
   if (ptr_kind != BSMM_PTR_HOST && ptr_kind != BSMM_PTR_DEVICE) return fail(BSMM_E_ARG, "bad ptr_kind");
   bsmm_status st = sync_sizes(C, reinterpret_cast<hipStream_t>(stream));
   if (st != BSMM_OK) return st;
+  if (C->stack_panelled)
+    return fail(BSMM_E_UNSUPPORTED, "the last multiply built its product stack in panels, which are not kept");
   if (!C->has_stack) {
     if (nprod) *nprod = 0;
     return BSMM_OK;
@@ -618,13 +638,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // allocates or synchronises (graph-capturable); the bounds are capacities.
   const bool reserved = C->cap_nnzb > 0;
   // scratch
-  if (C->flags.ensure(2) != hipSuccess || C->work.ensure(numeric_work_elems()) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
+  if (C->flags.ensure(3) != hipSuccess || C->work.ensure(numeric_work_elems()) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
     if (C->rows[x].ensure(nbrows + 1) != hipSuccess || C->pre[x].ensure(nbrows + 1) != hipSuccess)
       return fail(BSMM_E_NOMEM, "scratch allocation failed");
-  if (C->wide.ensure(std::max(nbrows, 1)) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
+  if (C->wide.ensure(std::max(nbrows, 1)) != hipSuccess || C->huge.ensure(std::max(nbrows, 1)) != hipSuccess)
+    return fail(BSMM_E_NOMEM, "scratch allocation failed");
   const double* normA = nullptr;
   const double* normB = nullptr;
   if (use_eps) {
@@ -642,7 +663,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       normB = C->norm_b.p;
     }
   }
-  HIP_TRY(launch_zero_u32(C->flags.p, 2, s));  // symbolic-pass flags and the wide-row count
+  HIP_TRY(launch_zero_u32(C->flags.p, 3, s));  // symbolic-pass flags, the wide- and huge-row counts
   mark(C, ev, 1, s);
 
   SymArgs g{};
@@ -664,6 +685,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.flags = C->flags.p;
   g.wide = C->wide.p;
   g.n_wide = reinterpret_cast<int32_t*>(C->flags.p + 1);
+  g.huge = C->huge.p;
+  g.n_huge = reinterpret_cast<int32_t*>(C->flags.p + 2);
   g.totals = C->totals.p;
   HIP_TRY(launch_sym_count(g, s));
   {
@@ -679,13 +702,23 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
                                C->flags.p, C->totals.p, s));
   mark(C, ev, 2, s);
 
+  // The 23x23 paths may build and consume the stack in panels of block rows
+  // (at most stack_limit products each); the other paths build it whole.
+  const bool panel_ok = uniform == 23;
+  int32_t npanels = 1;
   int64_t nnzc = 0, nprod = 0, nvals = 0, ncand = 0, nflop_half = 0;
-  int64_t nnzc_bound, nprod_bound, nvals_bound;
+  int64_t nnzc_bound, nprod_bound, nvals_bound, stack_bound;
   if (reserved) {
-    HIP_TRY(launch_check_capacity(C->totals.p, C->cap_nnzb, C->cap_nvals, C->cap_nprod, s));
+    npanels = panel_ok ? C->res_panels : 1;
+    HIP_TRY(launch_check_capacity(C->totals.p, C->cap_nnzb, C->cap_nvals, panel_ok ? C->cap_nprod : C->cap_stack,
+                                  npanels > 1 ? 1 : 0, s));
+    if (npanels > 1)
+      HIP_TRY(launch_panel_rows(C->pre[1].p, nbrows, std::max<int64_t>(C->cap_stack / 2, 1), npanels, C->cap_stack,
+                                C->panels.p, C->totals.p, s));
     nnzc_bound = C->cap_nnzb;
-    nprod_bound = C->cap_nprod;
+    nprod_bound = C->cap_stack;
     nvals_bound = C->cap_nvals;
+    stack_bound = C->cap_stack;
   } else {
     HIP_TRY(hipMemcpyAsync(C->h_totals, C->totals.p, kTotCount * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -701,7 +734,29 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       return fail(BSMM_E_UNSUPPORTED,
                   "a result block row would hold more than " + std::to_string(kMaxRowBlocks) + " blocks");
     if (nnzc > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "result has more than 2^31-1 blocks");
-    if (nprod > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "more than 2^31-1 block products");
+    stack_bound = nprod;
+    if (panel_ok && nprod > C->stack_limit) {
+      const int64_t np = panels_for(nprod, C->stack_limit);
+      if (np > kMaxPanels)
+        return fail(BSMM_E_CAPACITY, std::to_string(nprod) + " block products need more than " +
+                                         std::to_string(kMaxPanels) + " stack panels at the stack limit of " +
+                                         std::to_string(C->stack_limit) + " (bsmm_set_stack_limit)");
+      npanels = (int32_t)np;
+      if (C->panels.ensure(npanels + 1) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
+      HIP_TRY(launch_panel_rows(C->pre[1].p, nbrows, std::max<int64_t>(C->stack_limit / 2, 1), npanels,
+                                C->stack_limit, C->panels.p, C->totals.p, s));
+      HIP_TRY(hipMemcpyAsync(C->h_totals + kTotCount, C->totals.p + kTotPanelMax, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (C->h_totals[kTotCount] > C->stack_limit)
+        return fail(BSMM_E_CAPACITY, "a stack panel would hold " + std::to_string(C->h_totals[kTotCount]) +
+                                         " block products, above the stack limit of " +
+                                         std::to_string(C->stack_limit) +
+                                         " (a block row holds more than half of it; bsmm_set_stack_limit)");
+      stack_bound = C->stack_limit;
+    } else if (nprod > 0x7fffffffLL) {
+      return fail(BSMM_E_CAPACITY, "more than 2^31-1 block products");
+    }
     nnzc_bound = nnzc;
     nprod_bound = nprod;
     nvals_bound = nvals;
@@ -711,13 +766,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // and stack are rewritten.  A resource failure past this point leaves C a
   // valid empty matrix without a stack (empty_result).
   C->has_stack = false;
+  C->stack_panelled = false;
   // output storage: in place -> write the spare storage and swap afterwards
   const bool in_place = use_old && C_in == C;
   Storage& out = in_place ? C->spare : C->cur;
   if (ensure_storage(out, nbrows, nnzc_bound, nvals_bound) != hipSuccess ||
       C->prod_ptr.ensure(nnzc_bound + 1) != hipSuccess ||
-      C->prod_a.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
-      C->prod_b.ensure(std::max<int64_t>(nprod_bound, 1)) != hipSuccess ||
+      C->prod_a.ensure(std::max<int64_t>(stack_bound, 1)) != hipSuccess ||
+      C->prod_b.ensure(std::max<int64_t>(stack_bound, 1)) != hipSuccess ||
       C->old_idx.ensure(std::max<int64_t>(nnzc_bound, 1)) != hipSuccess)
     return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the result failed");
   const bool small = !split && !slice && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
@@ -760,8 +816,6 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.c_old_idx = C->old_idx.p;
   g.prod_a = C->prod_a.p;
   g.prod_b = C->prod_b.p;
-  HIP_W(launch_sym_fill(g, s));
-  mark(C, ev, 4, s);
 
   NumArgs na{};
   na.A = g.A;
@@ -782,33 +836,49 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
   na.wide_inner = (A->col_edges & 0x7fffu) == 0;  // no inner block edge below 16
+  na.c_row_ptr = out.row_ptr.p;
   ClassVariants variants{-1, -1, -1, -1};
-  if (split) {
-    HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
-    HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
-    HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, C->work.p, s));
-  } else if (slice) {
-    HIP_W(launch_slice_int8x7(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, A->cur.row_ptr.p, A->nbrows, nullptr,
-                                A->nbrows, C->slice_rowof.p, C->slice_ea.p, C->slice_a.p, s));
-    HIP_W(launch_slice_int8x7(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, nullptr, 0, B->cur.col_idx.p, B->nbcols,
-                                nullptr, C->slice_eb.p, C->slice_b.p, s));
-    HIP_W(launch_numeric_slice23(na, out.row_ptr.p, nbrows, C->slice_a.p, C->slice_b.p, C->slice_ea.p,
-                                   C->slice_eb.p, C->work.p, s));
-  } else if (small) {
-    HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
-                               C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
-    variants = tuned_variants(tune_key(A, B), std::max(A->max_edge, B->max_edge));
-    HIP_W(launch_small_plan(na, C, variants, s));
-    C->small_args = na;
-  } else {
-    HIP_W(launch_numeric(na, uniform, C->work.p, s));
+  // One pass per stack panel: fill the panel's rows (pattern and products),
+  // then multiply them.  With panels, the fill phase time covers the first
+  // panel's fill and the numeric phase everything after it.
+  for (int32_t pnl = 0; pnl < npanels; ++pnl) {
+    g.panel = npanels > 1 ? C->panels.p + pnl : nullptr;
+    na.panel = g.panel;
+    HIP_W(launch_sym_fill(g, s));
+    if (pnl == 0) mark(C, ev, 4, s);
+    if (split) {
+      if (pnl == 0) {
+        HIP_W(launch_split_bf16x3(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, C->split_a.p, s));
+        HIP_W(launch_split_bf16x3(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, C->split_b.p, s));
+      }
+      HIP_W(launch_numeric_split23(na, C->split_a.p, C->split_b.p, C->work.p, s));
+    } else if (slice) {
+      if (pnl == 0) {
+        HIP_W(launch_slice_int8x7(A->cur.values.p, A->dsz.p, blocks_bound(A), 0, A->cur.row_ptr.p, A->nbrows,
+                                    nullptr, A->nbrows, C->slice_rowof.p, C->slice_ea.p, C->slice_a.p, s));
+        HIP_W(launch_slice_int8x7(B->cur.values.p, B->dsz.p, blocks_bound(B), 1, nullptr, 0, B->cur.col_idx.p,
+                                    B->nbcols, nullptr, C->slice_eb.p, C->slice_b.p, s));
+      }
+      HIP_W(launch_numeric_slice23(na, out.row_ptr.p, nbrows, C->slice_a.p, C->slice_b.p, C->slice_ea.p,
+                                     C->slice_eb.p, C->work.p, s));
+    } else if (small) {
+      HIP_W(launch_class_lists(na, C->class_cnt.p, C->class_pre.p, C->scan_tmp.p, C->class_list.p,
+                                 C->class_start.p, C->class_np.p, C->class_q.p, C->prod_desc.p, s));
+      variants = tuned_variants(tune_key(A, B), std::max(A->max_edge, B->max_edge));
+      HIP_W(launch_small_plan(na, C, variants, s));
+      C->small_args = na;
+    } else {
+      HIP_W(launch_numeric(na, uniform, C->work.p, s));
+    }
   }
   mark(C, ev, 5, s);
   HIP_W(launch_finish_multiply(C->totals.p, out.values.p, C->dsz.p, s));
   mark(C, ev, 6, s);
 
   if (in_place) std::swap(C->cur, C->spare);
-  C->has_stack = true;
+  C->has_stack = npanels == 1;
+  C->stack_panelled = npanels > 1;
+  C->stats.panels = npanels;
   C->stats.path = split ? BSMM_PATH_SPLIT23 : slice ? BSMM_PATH_SLICE23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
   std::copy(variants.begin(), variants.end(), C->stats.variants);
   if (reserved) return BSMM_OK;
@@ -847,6 +917,7 @@ bsmm_status bsmm_filter(bsmm_mat m, double eps, void* stream) {
                         m->spare.row_ptr.p, m->spare.col_idx.p, m->spare.blk_off.p, m->spare.values.p, s));
   std::swap(m->cur, m->spare);
   m->has_stack = false;  // block indices changed
+  m->stack_panelled = false;
   if (reserved) return BSMM_OK;
   HIP_TRY(hipMemcpyAsync(m->h_totals, m->dsz.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -939,6 +1010,7 @@ bsmm_status bsmm_filter_noalloc(bsmm_mat m, double eps, void* stream) {
                         m->spare.blk_off.p, m->spare.values.p, s));
   std::swap(m->cur, m->spare);
   m->has_stack = false;  // block indices changed
+  m->stack_panelled = false;
   if (reserved) return BSMM_OK;
   int64_t sizes[2] = {0, 0};  // pageable host memory: a synchronous read-back, no allocation
   HIP_TRY(hipMemcpyAsync(sizes, m->dsz.p, sizeof(sizes), hipMemcpyDeviceToHost, s));
@@ -952,8 +1024,17 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
   g_err.clear();
   if (!m) return fail(BSMM_E_ARG, "NULL handle");
   if (max_nnzb < 1 || max_nvals < 1 || max_products < 1) return fail(BSMM_E_ARG, "capacities must be >= 1");
-  if (max_nnzb > 0x7fffffffLL || max_products > 0x7fffffffLL)
-    return fail(BSMM_E_CAPACITY, "block and product capacities are limited to 2^31-1");
+  if (max_nnzb > 0x7fffffffLL) return fail(BSMM_E_CAPACITY, "the block capacity is limited to 2^31-1");
+  // a uniform 23x23 output takes its products in stack panels of at most
+  // stack_limit entries; other outputs hold the whole stack
+  const bool panel_ok = m->uniform == 23;
+  if (!panel_ok && max_products > 0x7fffffffLL)
+    return fail(BSMM_E_CAPACITY, "the product capacity is limited to 2^31-1 unless the blocks are 23x23");
+  const int64_t cstack = panel_ok ? std::min(max_products, m->stack_limit) : max_products;
+  const int64_t npanels = cstack < max_products ? panels_for(max_products, m->stack_limit) : 1;
+  if (npanels > kMaxPanels)
+    return fail(BSMM_E_CAPACITY, "the product capacity needs more than " + std::to_string(kMaxPanels) +
+                                     " stack panels at the stack limit of " + std::to_string(m->stack_limit));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   bsmm_status st = sync_sizes(m, s);
   if (st != BSMM_OK) return st;
@@ -989,7 +1070,8 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
   // A's row and B's column edges, so an edge above kSmallEdge rules it out
   const bool small_ok = m->max_edge <= kSmallEdge;
   bool ok = ensure_storage(m->spare, nbrows, cb, cv) == hipSuccess && m->prod_ptr.ensure(cb + 1) == hipSuccess &&
-            m->prod_a.ensure(cp) == hipSuccess && m->prod_b.ensure(cp) == hipSuccess &&
+            m->prod_a.ensure(cstack) == hipSuccess && m->prod_b.ensure(cstack) == hipSuccess &&
+            m->panels.ensure(npanels + 1) == hipSuccess &&
             m->old_idx.ensure(cb) == hipSuccess &&
             (!small_ok ||
              (m->prod_desc.ensure(cp) == hipSuccess && m->class_list.ensure(2 * cb) == hipSuccess &&
@@ -997,15 +1079,14 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
               m->class_start.ensure(5) == hipSuccess && m->class_np.ensure(nce) == hipSuccess &&
               m->class_q.ensure(nce + 1) == hipSuccess)) &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
-            m->flags.ensure(2) == hipSuccess && m->work.ensure(numeric_work_elems()) == hipSuccess &&
+            m->flags.ensure(3) == hipSuccess && m->work.ensure(numeric_work_elems()) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&
             m->norm_self.ensure(cb) == hipSuccess && m->fkeep.ensure(cb + 1) == hipSuccess &&
             m->fvsz.ensure(cb + 1) == hipSuccess && m->fpos.ensure(cb + 1) == hipSuccess &&
-            m->fvoff.ensure(cb + 1) == hipSuccess && m->split_a.ensure(split_elems(cb)) == hipSuccess &&
-            m->split_b.ensure(split_elems(cb)) == hipSuccess;
+            m->fvoff.ensure(cb + 1) == hipSuccess;
   for (int x = 0; x < 5 && ok; ++x)
     ok = m->rows[x].ensure(nbrows + 1) == hipSuccess && m->pre[x].ensure(nbrows + 1) == hipSuccess;
-  ok = ok && m->wide.ensure(std::max(nbrows, 1)) == hipSuccess;
+  ok = ok && m->wide.ensure(std::max(nbrows, 1)) == hipSuccess && m->huge.ensure(std::max(nbrows, 1)) == hipSuccess;
   if (!ok) return fail(BSMM_E_NOMEM, "device allocation for the reservation failed");
   // counters read back before the first reserved multiply: zero
   if (!m->has_stack) {
@@ -1020,6 +1101,18 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
   m->cap_nnzb = cb;
   m->cap_nvals = cv;
   m->cap_nprod = cp;
+  m->cap_stack = cstack;
+  m->res_panels = (int32_t)npanels;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_set_stack_limit(bsmm_mat m, int64_t max_products) {
+  g_err.clear();
+  if (!m) return fail(BSMM_E_ARG, "NULL handle");
+  if (max_products < 2 || max_products > 0x7fffffffLL)
+    return fail(BSMM_E_ARG, "the stack limit must be in 2 .. 2^31-1 products");
+  if (m->cap_nnzb > 0) return fail(BSMM_E_ARG, "set the stack limit before bsmm_reserve");
+  m->stack_limit = max_products;
   return BSMM_OK;
 }
 

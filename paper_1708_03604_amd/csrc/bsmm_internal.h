@@ -20,11 +20,16 @@ struct MatView {
   const double* values;
 };
 
-// Symbolic row-pass limits (LDS-resident hash of one C block row).
+// Symbolic row-pass limits (LDS-resident hash of one C block row).  The
+// ordinary forms take rows of up to kLargeRowA stored A blocks and
+// kLargeRowBlocks result blocks; longer rows go to the huge forms (one
+// workgroup per CU), which take up to kMaxRowA and kMaxRowBlocks.
 constexpr int kSymThreads = 256;
-constexpr int kHashSlots = 2048;   // open-addressing table over block columns
-constexpr int kMaxRowBlocks = 1024; // result blocks per C block row
-constexpr int kMaxRowA = 1024;      // stored A blocks per block row
+constexpr int kHashSlots = 2048;       // open-addressing table over block columns (ordinary forms)
+constexpr int kLargeRowBlocks = 1024;  // result blocks per C block row, ordinary forms
+constexpr int kLargeRowA = 1024;       // stored A blocks per block row, ordinary forms
+constexpr int kMaxRowBlocks = 2048;    // result blocks per C block row
+constexpr int kMaxRowA = 2048;         // stored A blocks per block row
 
 // Device-side flags raised by kernels (bit mask in a uint32 word).
 enum : uint32_t {
@@ -43,6 +48,7 @@ enum : int {
   kTotFlags = 4,     // symbolic-pass flags
   kTotFlopHalf = 5,  // sum over kept products of m*n*k
   kTotAbort = 6,     // nonzero: the result does not fit; later kernels do nothing
+  kTotPanelMax = 7,  // most products of any stack panel (panelled multiplies)
   kTotCount = 8
 };
 
@@ -76,6 +82,13 @@ struct SymArgs {
   // the count pass in any order; *n_wide must be zero when the count pass starts
   int32_t* wide;       // [nbrows]
   int32_t* n_wide;
+  // rows the ordinary forms leave to the huge forms (listed the same way)
+  int32_t* huge;       // [nbrows]
+  int32_t* n_huge;
+  // fill pass: only rows [panel[0], panel[1]) are filled, and their products
+  // are written from stack position row_pstart[panel[0]] on at index 0 (the
+  // stack holds one panel of rows); nullptr = every row, one stack
+  const int32_t* panel;
   // fill pass inputs/outputs (exclusive prefixes of the counts, length nbrows+1)
   const int32_t* c_row_ptr;
   const int64_t* row_pstart;
@@ -105,6 +118,10 @@ struct NumArgs {
   const int32_t* prod_b;
   double* c_values;
   int wide_inner;          // every inner block edge >= 16: the generic path may use the matrix-core form
+  // 23x23 paths: only the C blocks of rows [panel[0], panel[1]) are computed,
+  // and prod_a/prod_b hold that panel's products from index 0; nullptr = all
+  const int32_t* panel;
+  const int32_t* c_row_ptr;
 };
 
 // Launchers (all enqueue on `s`; they return the launch status).
@@ -116,8 +133,18 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 // Zero the value slack after the result and write its size record
 // dsz = {nnzb, nvals, error bits}.
 hipError_t launch_finish_multiply(const int64_t* totals, double* values, int64_t* dsz, hipStream_t s);
+// Reserved multiply: abort (totals[kTotAbort]) if the counted result exceeds
+// the capacities or a row limit was met; with big_stack the products may
+// exceed 2^31-1 (the stack is built in panels).
 hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_nvals, int64_t cap_nprod,
-                                 hipStream_t s);
+                                 int big_stack, hipStream_t s);
+// Stacks in panels of rows (23x23 paths): panels[0..np] row bounds from the
+// per-row product prefix np_pre, each panel starting at a multiple of half
+// products; the largest panel's products go to totals[kTotPanelMax], and the
+// multiply is aborted if they exceed cap.  np <= kMaxPanels.
+constexpr int32_t kMaxPanels = 4096;
+hipError_t launch_panel_rows(const int64_t* np_pre, int32_t nbrows, int64_t half, int32_t np, int64_t cap,
+                             int32_t* panels, int64_t* totals, hipStream_t s);
 // Frobenius norm of the first *d_nvals values into out[0] (device); partial
 // needs frobenius_tmp_elems() doubles.
 int64_t frobenius_tmp_elems();
@@ -142,10 +169,19 @@ hipError_t launch_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t*
                                 int64_t* totals, hipStream_t s);
 // `work` holds numeric_work_elems() entries (the 23x23 kernels' schedule).
 int64_t numeric_work_elems();
-// Schedule of the 23x23 kernels (FP64, split, exact slices): slices of equal
-// product counts per XCD part into `work`; returns the slices per part.  The
-// kernels run on tile23_workgroups() workgroups of four waves.
-int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, int32_t* work, hipStream_t s);
+// Schedule of the 23x23 kernels (FP64, split, exact slices): the C blocks of
+// the panel (rows [panel[0], panel[1]) of c_row_ptr; all if panel is
+// nullptr) in kSliceParts parts of equal product counts, each cut into ns
+// slices, written to `work` (see k_product_slices); returns ns.  The kernels
+// run on tile23_workgroups() workgroups of four waves.
+constexpr int kSliceParts = 8;  // one per XCD
+int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, const int32_t* c_row_ptr,
+                              const int32_t* panel, int32_t* work, hipStream_t s);
+// Stack position that index 0 of prod_a/prod_b holds, stored after the
+// slice bounds by k_product_slices.
+__device__ __forceinline__ int64_t slices_pbase(const int32_t* bounds, int32_t ns) {
+  return *reinterpret_cast<const int64_t*>(bounds + kSliceParts * (ns + 1));
+}
 int32_t tile23_workgroups();
 hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hipStream_t s);
 

@@ -285,17 +285,63 @@ hipError_t launch_finish_multiply(const int64_t* totals, double* values, int64_t
 // Reserved capacity check: raises totals[kTotAbort] if the result does not fit
 // (or the symbolic pass flagged a row); every later kernel then does nothing.
 __global__ void k_check_capacity(int64_t* __restrict__ totals, int64_t cap_nnzb, int64_t cap_nvals,
-                                 int64_t cap_nprod) {
+                                 int64_t cap_nprod, int big_stack) {
   if (threadIdx.x != 0) return;
   const bool bad = totals[kTotFlags] != 0 || totals[kTotNnzc] > cap_nnzb || totals[kTotNvals] > cap_nvals ||
                    totals[kTotNprod] > cap_nprod || totals[kTotNnzc] > 0x7fffffffLL ||
-                   totals[kTotNprod] > 0x7fffffffLL;
+                   (!big_stack && totals[kTotNprod] > 0x7fffffffLL);
   totals[kTotAbort] = bad ? 1 : 0;
 }
 
 hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_nvals, int64_t cap_nprod,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, totals, cap_nnzb, cap_nvals, cap_nprod);
+                                 int big_stack, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(64), 0, s, totals, cap_nnzb, cap_nvals, cap_nprod, big_stack);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- stack panels
+
+// Row panels of a stack built and consumed in parts: panel p is rows
+// [panels[p], panels[p+1]) with panels[p] the first row whose products start
+// at or after p*half (np_pre: exclusive prefix of the per-row product
+// counts), panels[np] = nbrows.  A panel then holds at most half plus one
+// row's products.  totals[kTotPanelMax] receives the most products of any
+// panel; above cap the multiply is aborted (later kernels do nothing).
+__global__ __launch_bounds__(256) void k_panel_rows(const int64_t* __restrict__ np_pre, int32_t nbrows, int64_t half,
+                                                    int32_t np, int64_t cap, int32_t* __restrict__ panels,
+                                                    int64_t* __restrict__ totals) {
+  __shared__ int32_t bnd[kMaxPanels + 1];
+  __shared__ unsigned long long most;
+  if (threadIdx.x == 0) most = 0;
+  for (int32_t p = threadIdx.x; p <= np; p += blockDim.x) {
+    int32_t lo = 0, hi = nbrows;
+    if (p == np) {
+      lo = nbrows;
+    } else {
+      const int64_t t = (int64_t)p * half;
+      while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (np_pre[mid] < t) lo = mid + 1;
+        else hi = mid;
+      }
+    }
+    bnd[p] = lo;
+    panels[p] = lo;
+  }
+  __syncthreads();
+  for (int32_t p = threadIdx.x; p < np; p += blockDim.x)
+    atomicMax(&most, (unsigned long long)(np_pre[bnd[p + 1]] - np_pre[bnd[p]]));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    totals[kTotPanelMax] = (int64_t)most;
+    if ((int64_t)most > cap) totals[kTotAbort] = 1;
+  }
+}
+
+hipError_t launch_panel_rows(const int64_t* np_pre, int32_t nbrows, int64_t half, int32_t np, int64_t cap,
+                             int32_t* panels, int64_t* totals, hipStream_t s) {
+  if (np < 1 || np > kMaxPanels) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_panel_rows, dim3(1), dim3(256), 0, s, np_pre, nbrows, half, np, cap, panels, totals);
   return hipGetLastError();
 }
 

@@ -244,39 +244,49 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
 // ---------------------------------------------------------------------------
 constexpr int kTileEdge = 24;
 
-// First c in [0, n] with prod_ptr[c] >= t (prod_ptr is non-decreasing).
-__device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_t n, int64_t t) {
-  int32_t lo = 0, hi = n;
+// First c in [lo, hi] with prod_ptr[c] >= t (prod_ptr is non-decreasing),
+// hi if there is none.
+__device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_t lo, int32_t hi, int64_t t) {
   while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
+    const int32_t mid = lo + ((hi - lo) >> 1);
     if (prod_ptr[mid] < t) lo = mid + 1;
     else hi = mid;
   }
   return lo;
 }
 
-// Schedule of the 23x23 kernel: the C blocks are cut into 8 XCD parts of
-// equal product counts (XCD x: products [P x / 8, P (x+1) / 8)), and each
-// part into ns slices of equal product counts, cut at C block boundaries:
+// Schedule of the 23x23 kernels: the C blocks [c0, c1) of the panel (all
+// blocks without panels) are cut into 8 XCD parts of equal product counts
+// (XCD x: products [P x / 8, P (x+1) / 8) of the panel's P), and each part
+// into ns slices of equal product counts, cut at C block boundaries:
 // bounds[x (ns+1) + j] is the first C block of slice j of part x.  Waves
 // take every wpx-th slice of their XCD's part, so each wave gets about the
 // same number of products while an XCD still works on nearby block rows.
-constexpr int kKernelXcds = 8;
+// The panel's first stack position follows the bounds (slices_pbase).
+constexpr int kKernelXcds = kSliceParts;
 constexpr int kSlicesPerWave = 16;  // measured: 8 1.63 ms, 16 1.60, 32 1.65, 64 1.76 (molecules)
-__global__ void k_product_slices(const int64_t* __restrict__ prod_ptr, const int64_t* __restrict__ totals, int32_t ns,
+__global__ void k_product_slices(const int64_t* __restrict__ prod_ptr, const int64_t* __restrict__ totals,
+                                 const int32_t* __restrict__ c_row_ptr, const int32_t* __restrict__ panel, int32_t ns,
                                  int32_t* __restrict__ bounds) {
   const int32_t nnzc = live_nnzc(totals);
-  const int64_t P = prod_ptr[nnzc];
+  int32_t c0 = 0, c1 = nnzc;
+  if (panel && nnzc > 0) {
+    c0 = c_row_ptr[panel[0]];
+    c1 = c_row_ptr[panel[1]];
+  }
+  const int64_t pb = nnzc > 0 ? prod_ptr[c0] : 0;
+  const int64_t P = nnzc > 0 ? prod_ptr[c1] - pb : 0;
   const int32_t per = ns + 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<int64_t*>(bounds + kKernelXcds * per) = pb;
   for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < kKernelXcds * per; t += gridDim.x * 256) {
     const int32_t x = t / per, j = t - x * per;
-    const int64_t p0 = P * x / kKernelXcds, p1 = P * (x + 1) / kKernelXcds;
-    const int32_t X0 = lower_bound_c(prod_ptr, nnzc, p0);
-    const int32_t X1 = x == kKernelXcds - 1 ? nnzc : lower_bound_c(prod_ptr, nnzc, p1);
+    const int64_t p0 = pb + P * x / kKernelXcds, p1 = pb + P * (x + 1) / kKernelXcds;
+    const int32_t X0 = x == 0 ? c0 : lower_bound_c(prod_ptr, c0, c1, p0);
+    const int32_t X1 = x == kKernelXcds - 1 ? c1 : lower_bound_c(prod_ptr, c0, c1, p1);
     int32_t b;
     if (j == 0) b = X0;
     else if (j == ns) b = X1;
-    else b = min(X1, max(X0, lower_bound_c(prod_ptr, nnzc, p0 + (p1 - p0) * j / ns)));
+    else b = min(X1, max(X0, lower_bound_c(prod_ptr, c0, c1, p0 + (p1 - p0) * j / ns)));
     bounds[t] = b;
   }
 }
@@ -343,6 +353,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
   const int32_t* const bnd = bounds + xcd * (ns + 1);
+  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod_a[0]
 
   // fetch cursor: slice iq, products [ip, ip_end)
   int32_t iq = wix;
@@ -364,13 +375,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   {
     const int64_t n0 = next_index();
     if (n0 >= 0) {
-      qa0 = prod_a[n0];
-      qb0 = prod_b[n0];
+      qa0 = prod_a[n0 - pbase];
+      qb0 = prod_b[n0 - pbase];
     }
     const int64_t n1 = next_index();
     if (n1 >= 0) {
-      qa1 = prod_a[n1];
-      qb1 = prod_b[n1];
+      qa1 = prod_a[n1 - pbase];
+      qb1 = prod_b[n1 - pbase];
     }
   }
   double opa[PER], opb[PER];
@@ -389,8 +400,8 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
     qa0 = qa1;
     qb0 = qb1;
     const int64_t n = next_index();
-    qa1 = n >= 0 ? prod_a[n] : -1;
-    qb1 = n >= 0 ? prod_b[n] : -1;
+    qa1 = n >= 0 ? prod_a[n - pbase] : -1;
+    qb1 = n >= 0 ? prod_b[n - pbase] : -1;
   };
   auto stage_write = [&](const int st) {
     double* base = &lds[wv][st][0];
@@ -538,13 +549,15 @@ static int32_t tile23_grid() {
 
 int64_t numeric_work_elems() {
   const int64_t ns = (int64_t)tile23_grid() / kKernelXcds * 4 * kSlicesPerWave;
-  return kKernelXcds * (ns + 1);
+  return kKernelXcds * (ns + 1) + 2;  // bounds, then the int64 stack base (at byte 32 (ns + 1): aligned)
 }
 
-int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, int32_t* work, hipStream_t s) {
+int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, const int32_t* c_row_ptr,
+                              const int32_t* panel, int32_t* work, hipStream_t s) {
   const int32_t ns = tile23_grid() / kKernelXcds * 4 * kSlicesPerWave;
   const int32_t n = kKernelXcds * (ns + 1);
-  hipLaunchKernelGGL(k_product_slices, dim3((n + 255) / 256), dim3(256), 0, s, prod_ptr, totals, ns, work);
+  hipLaunchKernelGGL(k_product_slices, dim3((n + 255) / 256), dim3(256), 0, s, prod_ptr, totals, c_row_ptr, panel,
+                     ns, work);
   return ns;
 }
 
@@ -554,7 +567,7 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
   if (a.nnzc_bound <= 0) return hipSuccess;
   if (uniform_size == 23) {
     const int32_t blocks = tile23_grid();
-    const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, work, s);
+    const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, a.c_row_ptr, a.panel, work, s);
     hipLaunchKernelGGL(k_numeric_mfma24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
                        a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
                        a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);

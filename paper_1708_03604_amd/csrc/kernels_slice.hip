@@ -179,11 +179,12 @@ __global__ __launch_bounds__(256, 2) void k_numeric_slice23(
 
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
-  constexpr int kXcds = 8;
+  constexpr int kXcds = kSliceParts;
   const int32_t xcd = blockIdx.x % kXcds;
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
   const int32_t* const bnd = bounds + xcd * (ns + 1);
+  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod_a[0]
 
   // fetch cursor: slice iq of the XCD's part, products [ip, ip_end)
   int32_t iq = wix;
@@ -205,13 +206,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_slice23(
   {
     const int64_t n0 = next_index();
     if (n0 >= 0) {
-      qa0 = prod_a[n0];
-      qb0 = prod_b[n0];
+      qa0 = prod_a[n0 - pbase];
+      qb0 = prod_b[n0 - pbase];
     }
     const int64_t n1 = next_index();
     if (n1 >= 0) {
-      qa1 = prod_a[n1];
-      qb1 = prod_b[n1];
+      qa1 = prod_a[n1 - pbase];
+      qb1 = prod_b[n1 - pbase];
     }
   }
   u32x4 opa0[kPer], opb0[kPer], opa1[kPer], opb1[kPer];
@@ -233,8 +234,8 @@ __global__ __launch_bounds__(256, 2) void k_numeric_slice23(
     qa0 = qa1;
     qb0 = qb1;
     const int64_t n = next_index();
-    qa1 = n >= 0 ? prod_a[n] : -1;
-    qb1 = n >= 0 ? prod_b[n] : -1;
+    qa1 = n >= 0 ? prod_a[n - pbase] : -1;
+    qb1 = n >= 0 ? prod_b[n - pbase] : -1;
   };
   auto stage_write = [&](const u32x4(&opa)[kPer], const u32x4(&opb)[kPer]) __attribute__((always_inline)) {
 #pragma unroll
@@ -379,7 +380,7 @@ hipError_t launch_numeric_slice23(const NumArgs& a, const int32_t* c_row_ptr, in
                                   const uint8_t* Bs, const int32_t* ea, const int32_t* eb, int32_t* work,
                                   hipStream_t s) {
   if (a.nnzc_bound <= 0) return hipSuccess;
-  const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, work, s);
+  const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, a.c_row_ptr, a.panel, work, s);
   hipLaunchKernelGGL(k_numeric_slice23, dim3(tile23_workgroups()), dim3(256), 0, s, As, Bs, ea, eb, c_row_ptr,
                      nbrows, a.c_col_idx, a.use_old ? a.Cin.values : a.c_values, a.prod_ptr, a.prod_a, a.prod_b,
                      a.c_old_idx, a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);

@@ -18,9 +18,17 @@
 namespace bsmm {
 
 constexpr int kHashBits = 11;
+constexpr int kHugeHashBits = 12;  // huge forms: 4096 slots, at most half full
 static_assert((1 << kHashBits) == kHashSlots, "hash size");
-static_assert(kMaxRowA % kSymThreads == 0, "A chunking");
-static_assert(kMaxRowBlocks % kSymThreads == 0, "row chunking");
+static_assert(kLargeRowA % kSymThreads == 0 && kMaxRowA % kSymThreads == 0, "A chunking");
+static_assert(kLargeRowBlocks % kSymThreads == 0 && kMaxRowBlocks % kSymThreads == 0, "row chunking");
+static_assert(2 * kLargeRowBlocks <= kHashSlots && 2 * kMaxRowBlocks <= (1 << kHugeHashBits), "hash load");
+
+// Rows of the current fill panel, and the stack position its index 0 holds.
+__device__ __forceinline__ bool in_panel(const SymArgs& g, int32_t i) {
+  return !g.panel || (i >= g.panel[0] && i < g.panel[1]);
+}
+__device__ __forceinline__ int64_t panel_base(const SymArgs& g) { return g.panel ? g.row_pstart[g.panel[0]] : 0; }
 
 template <int HB>
 __device__ __forceinline__ uint32_t hash_of(int32_t j) { return ((uint32_t)j * 2654435761u) >> (32 - HB); }
@@ -160,12 +168,12 @@ __device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA<RA>& r
 // flight per thread (rows of thousands of candidates are latency-bound).
 constexpr int kCandBatch = 4;
 
-// LDS of one workgroup of the count pass.  The hash always has the full size
-// (the row's distinct columns are what the pass counts); the A entries of
-// the row take RA slots.
-template <int RA>
+// LDS of one workgroup of the count pass.  The hash always has the form's
+// full size (the row's distinct columns are what the pass counts); the A
+// entries of the row take RA slots.
+template <int RA, int HB>
 struct CountShared {
-  int32_t hkey[kHashSlots];
+  int32_t hkey[1 << HB];
   RowA<RA> ra;
   int32_t s_nc;
   unsigned long long s_sumn;
@@ -174,9 +182,11 @@ struct CountShared {
   int s_bad;
 };
 
-// Count C block row i (one workgroup).
-template <int RA>
-__device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
+// Count C block row i (one workgroup).  A row beyond the form's limits (more
+// than RA A blocks, more than RC distinct columns) is listed for the huge
+// form when DEFER is set (nothing else is written), else flagged.
+template <int RA, int HB, int RC, bool DEFER>
+__device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) {
   int32_t* const hkey = sh.hkey;
   RowA<RA>& ra = sh.ra;
   int32_t& s_nc = sh.s_nc;
@@ -186,7 +196,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
   int& s_bad = sh.s_bad;
   const int tid = threadIdx.x;
   {
-    for (int h = tid; h < kHashSlots; h += kSymThreads) hkey[h] = -1;
+    for (int h = tid; h < (1 << HB); h += kSymThreads) hkey[h] = -1;
     if (tid == 0) {
       s_nc = 0;
       s_sumn = 0;
@@ -198,7 +208,9 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
     int32_t a0, nA;
     const int32_t T = load_row(g, i, ra, &a0, &nA);
     if (T < 0) {
-      if (tid == 0) {
+      if (DEFER) {
+        if (tid == 0) g.huge[atomicAdd(g.n_huge, 1)] = i;
+      } else if (tid == 0) {
         atomicOr(g.flags, kFlagRowTooManyA);
         g.row_nc[i] = 0;
         g.row_np[i] = 0;
@@ -231,7 +243,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
         const int32_t j = jj[u];
         nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[pp[u]];
         bool fresh;
-        const int h = hash_insert<kHashBits>(hkey, j, &fresh);
+        const int h = hash_insert<HB>(hkey, j, &fresh);
         if (h < 0) {
           s_bad = 1;
         } else if (fresh) {
@@ -245,7 +257,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
       for (int32_t q = g.Cin.row_ptr[i] + tid; q < o1; q += kSymThreads) {
         const int32_t j = g.Cin.col_idx[q];
         bool fresh;
-        const int h = hash_insert<kHashBits>(hkey, j, &fresh);
+        const int h = hash_insert<HB>(hkey, j, &fresh);
         if (h < 0) {
           s_bad = 1;
         } else if (fresh) {
@@ -260,13 +272,17 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA>& sh) {
     }
     __syncthreads();
     if (tid == 0) {
-      const bool bad = s_bad || s_nc > kMaxRowBlocks;
-      if (bad) atomicOr(g.flags, kFlagRowTooManyC);
-      g.row_nc[i] = bad ? 0 : s_nc;
-      g.row_np[i] = bad ? 0 : (int64_t)s_np;
-      g.row_nv[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_sumn;
-      g.row_ncand[i] = T;
-      g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
+      const bool bad = s_bad || s_nc > RC;
+      if (bad && DEFER) {
+        g.huge[atomicAdd(g.n_huge, 1)] = i;
+      } else {
+        if (bad) atomicOr(g.flags, kFlagRowTooManyC);
+        g.row_nc[i] = bad ? 0 : s_nc;
+        g.row_np[i] = bad ? 0 : (int64_t)s_np;
+        g.row_nv[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_sumn;
+        g.row_ncand[i] = T;
+        g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
+      }
     }
     __syncthreads();
   }
@@ -411,15 +427,22 @@ __global__ __launch_bounds__(256) void k_sym_count_thin(SymArgs g) {
   g.row_nf[i] = m * (int64_t)r.nf;
 }
 
-// Fill pass of the thin rows.
+// Fill pass of the thin rows.  With panels it also closes the panel's
+// product offsets: the entry of the first C block after the panel gets the
+// start of the next row's products (the value that row's fill writes later),
+// which the numeric kernels read as the panel's end.
 __global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
   if (g.totals[kTotAbort]) return;
+  if (g.panel && blockIdx.x == 0 && threadIdx.x == 0)
+    g.prod_ptr[g.c_row_ptr[g.panel[1]]] = g.row_pstart[g.panel[1]];
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= g.A.nbrows) return;
+  if (!in_panel(g, i)) return;
   ThinRow r;
   if (!thin_load(g, i, r)) return;
   const int32_t crow = g.c_row_ptr[i];
   const int64_t prow = g.row_pstart[i], vrow = g.row_vstart[i];
+  const int64_t srow = prow - panel_base(g);  // stack position of the row's first product
   const int64_t m = g.c_row_sizes[i];
   int64_t pc = 0, vc = 0;
 #pragma unroll
@@ -437,8 +460,8 @@ __global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
 #pragma unroll
       for (int y = 0; y < kThinT; ++y) {
         if (y < r.n && r.cj[y] == j) {
-          g.prod_a[prow + pc] = r.a0 + r.cp[y];
-          g.prod_b[prow + pc] = r.cq[y];
+          g.prod_a[srow + pc] = r.a0 + r.cp[y];
+          g.prod_b[srow + pc] = r.cq[y];
           ++pc;
         }
       }
@@ -452,12 +475,12 @@ constexpr int kCountSmallRowA = 256;
 // Small form (13 KB of LDS, eight workgroups per CU): the listed (not thin)
 // rows of at most 256 A blocks, one workgroup per row.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
-  __shared__ CountShared<kCountSmallRowA> sh;
+  __shared__ CountShared<kCountSmallRowA, kHashBits> sh;
   const int32_t nw = *g.n_wide;
   for (int32_t x = blockIdx.x; x < nw; x += gridDim.x) {
     const int32_t i = g.wide[x];
     if (g.A.row_ptr[i + 1] - g.A.row_ptr[i] > kCountSmallRowA) continue;  // uniform
-    count_row<kCountSmallRowA>(g, i, sh);
+    count_row<kCountSmallRowA, kHashBits, kLargeRowBlocks, true>(g, i, sh);
   }
 }
 
@@ -466,7 +489,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_small(SymArgs g) {
 // them at a time, one per thread, and counts the long rows in turn, so long
 // rows spread over the whole grid while short ones cost one load each.
 __global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
-  __shared__ CountShared<kMaxRowA> sh;
+  __shared__ CountShared<kLargeRowA, kHashBits> sh;
   __shared__ int32_t rows[kSymThreads];
   __shared__ int32_t nrows;
   const int tid = threadIdx.x;
@@ -481,8 +504,18 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_large(SymArgs g) {
       rows[atomicAdd(&nrows, 1)] = i;
     __syncthreads();
     const int32_t n = nrows;
-    for (int32_t x = 0; x < n; ++x) count_row<kMaxRowA>(g, rows[x], sh);
+    for (int32_t x = 0; x < n; ++x) count_row<kLargeRowA, kHashBits, kLargeRowBlocks, true>(g, rows[x], sh);
   }
+}
+
+// Huge form (56 KB of LDS): the rows the other forms listed in g.huge (more
+// than kLargeRowA A blocks or kLargeRowBlocks result blocks), one workgroup
+// per row; rows beyond kMaxRowA / kMaxRowBlocks are flagged.
+__global__ __launch_bounds__(kSymThreads) void k_sym_count_huge(SymArgs g) {
+  __shared__ CountShared<kMaxRowA, kHugeHashBits> sh;
+  const int32_t nh = *g.n_huge;
+  for (int32_t x = blockIdx.x; x < nh; x += gridDim.x)
+    count_row<kMaxRowA, kHugeHashBits, kMaxRowBlocks, false>(g, g.huge[x], sh);
 }
 
 // ------------------------------------------------------------------ fill
@@ -514,7 +547,8 @@ using FillSmall = FillCaps<10, 256, 512, 4096>;
 struct FillNone {  // no form: no row fits
   static constexpr int kRowA = -1, kRowC = -1;
 };
-using FillLarge = FillCaps<kHashBits, kMaxRowA, kMaxRowBlocks, 8192>;
+using FillLarge = FillCaps<kHashBits, kLargeRowA, kLargeRowBlocks, 8192>;
+using FillHuge = FillCaps<kHugeHashBits, kMaxRowA, kMaxRowBlocks, 8192>;
 
 template <int RA>
 __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, int32_t* a0_out, int32_t* na_out) {
@@ -718,7 +752,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
     uint32_t* const rmask = reinterpret_cast<uint32_t*>(svs);
     for (int r = tid; r < nC; r += kSymThreads) rmask[r] = 0;
     __syncthreads();
-    const int64_t prow = g.row_pstart[i];
+    const int64_t prow = g.row_pstart[i] - panel_base(g);  // stack position of the row's first product
     for (int32_t t0 = 0; t0 < T; t0 += kCandCacheF) {
       const int32_t t1 = T - t0 > kCandCacheF ? t0 + kCandCacheF : T;
       if (!one_chunk) {
@@ -800,15 +834,15 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_form(SymArgs g) {
   for (int32_t x = blockIdx.x; x < nw; x += gridDim.x) {
     const int32_t i = g.wide[x];
     // uniform: every thread reads the same sizes
-    if (!fill_fits<Cap>(g, i) || fill_fits<Below>(g, i)) continue;
+    if (!in_panel(g, i) || !fill_fits<Cap>(g, i) || fill_fits<Below>(g, i)) continue;
     fill_row<Cap>(g, i, sh);
     __syncthreads();
   }
 }
 
-// Large form: the remaining rows, found as in the count pass (workgroup w of
-// G looks at list entries w, w+G, ... 256 at a time and fills the rows the
-// small forms leave).
+// Large form: the rows the small forms leave that fit it, found as in the
+// count pass (workgroup w of G looks at list entries w, w+G, ... 256 at a
+// time).
 __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
   __shared__ FillShared<FillLarge> sh;
   __shared__ int32_t rows[kSymThreads];
@@ -822,13 +856,28 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_large(SymArgs g) {
     __syncthreads();
     const int64_t x = x0 + G * tid;
     const int32_t i = x < nw ? g.wide[x] : 0;
-    if (x < nw && !fill_fits_small(g, i)) rows[atomicAdd(&nrows, 1)] = i;
+    if (x < nw && in_panel(g, i) && !fill_fits_small(g, i) && fill_fits<FillLarge>(g, i))
+      rows[atomicAdd(&nrows, 1)] = i;
     __syncthreads();
     const int32_t n = nrows;
     for (int32_t x = 0; x < n; ++x) {
       fill_row<FillLarge>(g, rows[x], sh);
       __syncthreads();
     }
+  }
+}
+
+// Huge form (136 KB of LDS, one workgroup per CU): the rows the count pass
+// listed in g.huge, one workgroup per row.
+__global__ __launch_bounds__(kSymThreads) void k_sym_fill_huge(SymArgs g) {
+  __shared__ FillShared<FillHuge> sh;
+  if (g.totals[kTotAbort]) return;
+  const int32_t nh = *g.n_huge;
+  for (int32_t x = blockIdx.x; x < nh; x += gridDim.x) {
+    const int32_t i = g.huge[x];
+    if (!in_panel(g, i)) continue;  // uniform
+    fill_row<FillHuge>(g, i, sh);
+    __syncthreads();
   }
 }
 
@@ -842,6 +891,9 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sym_count_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sym_count_huge, dim3(a.A.nbrows < 1024 ? a.A.nbrows : 1024), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -858,6 +910,9 @@ hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sym_fill_huge, dim3(a.A.nbrows < 512 ? a.A.nbrows : 512), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -262,16 +262,16 @@ def test_error_paths():
 
 @pytest.mark.parametrize("case", ["a_row_too_long", "c_row_too_wide"])
 def test_row_limits_reported(case):
-    # more than 1024 stored A blocks in a row, or more than 1024 result blocks
+    # more than 2048 stored A blocks in a row, or more than 2048 result blocks
     # in a row: BSMM_E_UNSUPPORTED, and the other rows do not matter
     if case == "a_row_too_long":
-        ma = np.zeros((3, 1100), dtype=bool)
+        ma = np.zeros((3, 2100), dtype=bool)
         ma[1, :] = True
-        mb = np.zeros((1100, 2), dtype=bool)
+        mb = np.zeros((2100, 2), dtype=bool)
         mb[:, 0] = True
     else:
         ma = np.ones((3, 2), dtype=bool)
-        mb = np.ones((2, 1100), dtype=bool)
+        mb = np.ones((2, 2100), dtype=bool)
     A = W.with_pattern(np.ones(ma.shape[0], np.int32), np.ones(ma.shape[1], np.int32), *W.pattern_from_mask(ma))
     B = W.with_pattern(np.ones(mb.shape[0], np.int32), np.ones(mb.shape[1], np.int32), *W.pattern_from_mask(mb))
     dA, dB = bsmm.Matrix.from_csr(A), bsmm.Matrix.from_csr(B)
