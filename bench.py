@@ -405,17 +405,25 @@ def chain_leg(nmol, steps=12, eps=1e-7, replays=3, prec=None):
     prec = bsmm.BSMM_FP64 if prec is None else prec
     X0, info = W.symmetric_scaled(nmol=nmol)
     ch = SignChain(X0, steps=steps, eps=eps, prec=prec)
-    flops, prods, blocks = ch.count_flops()
+    t0 = time.perf_counter()
+    flops, prods, blocks = ch.count_flops(
+        progress=lambda k, nb: log(f"[bench] counting run: step {k + 1} done, X has {nb} blocks, "
+                                   f"{time.perf_counter() - t0:.1f} s"))
     # the same chain enqueued call by call (no graph), for comparison
     t0 = time.perf_counter()
     ch.enqueue()
     ch.stream.synchronize()
     dt_eager = time.perf_counter() - t0
+    log(f"[bench] eager chain: {dt_eager:.2f} s")
     ch.capture()
     ch.stream.synchronize()
+    log("[bench] chain captured")
     t0 = time.perf_counter()
-    for _ in range(replays):
+    for r in range(replays):
         ch.replay()
+        if replays > 1:
+            ch.stream.synchronize()
+            log(f"[bench] replay {r + 1} done")
     ch.stream.synchronize()
     dt = (time.perf_counter() - t0) / replays
     res = float(ch.residual.cpu()[0])

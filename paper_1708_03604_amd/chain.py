@@ -80,10 +80,11 @@ class SignChain:
         bsmm.bsmm_frobenius(self.R.handle, self.residual, st)
         self.final = cur
 
-    def count_flops(self):
+    def count_flops(self, progress=None):
         """Run the chain eagerly, reading each multiply's counters (one host
         synchronisation per multiply); returns (useful flops of the whole
-        chain, kept products, list of result block counts per step)."""
+        chain, kept products, list of result block counts per step).
+        progress(step, blocks), if given, is called after every step."""
         st = self.stream
         cur = self.X0
         flops, prods, blocks = 0.0, 0, []
@@ -96,6 +97,8 @@ class SignChain:
                 prods += s["products"]
                 bsmm.bsmm_filter(args[5].handle, self.eps, st)
             blocks.append(nxt.info()[2])
+            if progress is not None:
+                progress(k, blocks[-1])
             cur = nxt
         bsmm.multiply(1.0, cur, cur, -1.0, self.I1, self.R, 0.0, stream=st)
         s = bsmm.bsmm_stats(self.R.handle)

@@ -141,15 +141,27 @@ __device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* 
   return (int32_t)total;
 }
 
-// Candidate t of the row -> (A entry p, B block q).
+// Candidate t of the row -> (A entry p, B block q), p the last entry with
+// pre[p] <= t, found from *hint (an entry with pre[*hint] <= t: each thread
+// meets its candidates in increasing order) by trying the next two entries
+// before a binary search; *hint becomes p.
 template <int RA>
-__device__ __forceinline__ void candidate(const RowA<RA>& ra, int32_t nA, int32_t t, int32_t* p_out, int32_t* q_out) {
-  int lo = 0, hi = nA - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ra.pre[mid] <= t) lo = mid;
-    else hi = mid - 1;
+__device__ __forceinline__ void candidate(const RowA<RA>& ra, int32_t nA, int32_t t, int32_t* hint, int32_t* p_out,
+                                          int32_t* q_out) {
+  int lo = *hint;
+  if (lo + 1 < nA && ra.pre[lo + 1] <= t) {
+    ++lo;
+    if (lo + 1 < nA && ra.pre[lo + 1] <= t) {
+      int hi = nA - 1;
+      ++lo;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ra.pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+    }
   }
+  *hint = lo;
   *p_out = lo;
   *q_out = ra.qs[lo] + (t - ra.pre[lo]);
 }
@@ -223,6 +235,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
     }
     uint32_t np = 0;
     uint64_t nf = 0;
+    int32_t hint = 0;  // A entry of this thread's last candidate
     // kCandBatch candidates per thread at a time, their global loads issued together
     for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
       int32_t pp[kCandBatch], jj[kCandBatch];
@@ -231,7 +244,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
       for (int u = 0; u < kCandBatch; ++u) {
         const int32_t t = tb + u * kSymThreads;
         int32_t p = 0, q = 0;
-        if (t < T) candidate(ra, nA, t, &p, &q);
+        if (t < T) candidate(ra, nA, t, &hint, &p, &q);
         pp[u] = p;
         kk[u] = t < T && keep_product(g, ra, p, q);
         jj[u] = t < T ? g.B.col_idx[q] : 0;
@@ -588,15 +601,31 @@ __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, i
   return (int32_t)total;
 }
 
+// The A entry of candidate t: the last entry p in [lo, hi] with pre[p] <= t.
 template <int RA>
-__device__ __forceinline__ int32_t fill_entry_of(const RowFill<RA>& ra, int32_t nA, int32_t t) {
-  int lo = 0, hi = nA - 1;
+__device__ __forceinline__ int32_t fill_entry_in(const RowFill<RA>& ra, int32_t lo, int32_t hi, int32_t t) {
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (ra.pre[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
+}
+
+template <int RA>
+__device__ __forceinline__ int32_t fill_entry_of(const RowFill<RA>& ra, int32_t nA, int32_t t) {
+  return fill_entry_in(ra, 0, nA - 1, t);
+}
+
+// The same from an entry `hint` with pre[hint] <= t (each thread meets its
+// candidates in increasing order): the next two entries are tried before a
+// binary search over the rest, so long B rows cost one LDS read per
+// candidate instead of a search.
+template <int RA>
+__device__ __forceinline__ int32_t fill_entry_from(const RowFill<RA>& ra, int32_t nA, int32_t hint, int32_t t) {
+  if (hint + 1 >= nA || ra.pre[hint + 1] > t) return hint;
+  if (hint + 2 >= nA || ra.pre[hint + 2] > t) return hint + 1;
+  return fill_entry_in(ra, hint + 2, nA - 1, t);
 }
 
 template <int RA>
@@ -657,13 +686,14 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
     const int32_t T = load_row_fill(g, i, ra, &a0, &nA);
     if (T < 0) return;  // uniform over the workgroup; reported by the count pass
     const bool one_chunk = T <= kCandCacheF;
+    int32_t hint = 0;  // A entry of this thread's last candidate
     for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
       int32_t jj[kCandBatch];
       bool kk[kCandBatch];
 #pragma unroll
       for (int u = 0; u < kCandBatch; ++u) {
         const int32_t t = tb + u * kSymThreads;
-        const int32_t p = t < T ? fill_entry_of(ra, nA, t) : 0;
+        const int32_t p = t < T ? (hint = fill_entry_from(ra, nA, hint, t)) : 0;
         const int32_t q = ra.qs[p] + (t - ra.pre[p]);
         kk[u] = t < T && fill_keep(g, ra, p, q);
         jj[u] = t < T ? g.B.col_idx[q] : 0;
@@ -753,6 +783,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
     for (int r = tid; r < nC; r += kSymThreads) rmask[r] = 0;
     __syncthreads();
     const int64_t prow = g.row_pstart[i] - panel_base(g);  // stack position of the row's first product
+    int32_t chint = 0;  // A entry of this thread's last candidate in the chunk passes
     for (int32_t t0 = 0; t0 < T; t0 += kCandCacheF) {
       const int32_t t1 = T - t0 > kCandCacheF ? t0 + kCandCacheF : T;
       if (!one_chunk) {
@@ -762,7 +793,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
 #pragma unroll
           for (int u = 0; u < kCandBatch; ++u) {
             const int32_t t = tb + u * kSymThreads;
-            const int32_t p = t < t1 ? fill_entry_of(ra, nA, t) : 0;
+            const int32_t p = t < t1 ? (chint = fill_entry_from(ra, nA, chint, t)) : 0;
             const int32_t q = ra.qs[p] + (t - ra.pre[p]);
             kk[u] = t < t1 && fill_keep(g, ra, p, q);
             jj[u] = t < t1 ? g.B.col_idx[q] : 0;
@@ -786,16 +817,20 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
         const int32_t r1 = r0 + 32 <= pl + 1 ? r0 + 32 : pl + 1;
         const int32_t tb = ra.pre[r0] > t0 ? ra.pre[r0] : t0;
         const int32_t te = ra.pre[r1] < t1 ? ra.pre[r1] : t1;
+        int32_t rh = r0;  // pre[r0] <= tb: a valid hint for every candidate of the round
         for (int32_t t = tb + tid; t < te; t += kSymThreads) {
           const int h = cslot[t - t0];
-          if (h >= 0) atomicOr(&rmask[hcnt[h]], 1u << (fill_entry_of(ra, nA, t) - r0));
+          rh = fill_entry_from(ra, nA, rh, t);
+          if (h >= 0) atomicOr(&rmask[hcnt[h]], 1u << (rh - r0));
         }
         __syncthreads();
+        rh = r0;
         for (int32_t t = tb + tid; t < te; t += kSymThreads) {
           const int h = cslot[t - t0];
+          rh = fill_entry_from(ra, nA, rh, t);
           if (h >= 0) {
             const int r = hcnt[h];
-            const int32_t p = fill_entry_of(ra, nA, t);
+            const int32_t p = rh;
             const uint32_t below = rmask[r] & ((1u << (p - r0)) - 1u);
             const int32_t pos = spre[r] + cursor[r] + __builtin_popcount(below);
             g.prod_a[prow + pos] = a0 + p;
