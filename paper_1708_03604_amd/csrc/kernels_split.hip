@@ -48,30 +48,50 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 
 __device__ __forceinline__ double bf16_value(uint16_t h) { return (double)__uint_as_float((uint32_t)h << 16); }
 
-// One thread per stored BF16 position of every block: (block, row, col).
+// One wave per block: the 529 values are read with coalesced loads, split in
+// registers, placed in LDS in the stored layout (three slices of 23 rows x
+// 24 BF16, B transposed, the 24th column zero) and written out as 16-byte
+// chunks, so both the reads and the writes are contiguous.
 __global__ __launch_bounds__(256) void k_split_bf16x3(const double* __restrict__ values,
                                                       const int64_t* __restrict__ d_nnzb, int transpose,
                                                       uint16_t* __restrict__ out) {
+  __shared__ __align__(16) uint16_t tile[4][kSplitBlock];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint16_t* const t = tile[wv];
   const int64_t nnzb = *d_nnzb;
-  const int64_t total = nnzb * kSlice;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
-    const int64_t b = t / kSlice;
-    const int rc = (int)(t - b * kSlice);
-    const int r = rc / kRowPad, c = rc - r * kRowPad;  // stored row r, column c
-    double x = 0.0;
-    if (c < kE) x = transpose ? values[b * kE * kE + c * kE + r] : values[b * kE * kE + r * kE + c];
-    const uint16_t h0 = bf16_bits((float)x);
-    const double r1 = x - bf16_value(h0);
-    const uint16_t h1 = bf16_bits((float)r1);
-    const double r2 = r1 - bf16_value(h1);
-    const uint16_t h2 = bf16_bits((float)r2);
-    uint16_t* o = out + b * kSplitBlock + rc;
-    o[0] = h0;
-    o[kSlice] = h1;
-    o[2 * kSlice] = h2;
+  // the pad column (stored column 23 of every row of every slice) is never
+  // written below: zero it once
+  for (int x = lane; x < 3 * kE; x += 64) t[(x / kE) * kSlice + (x % kE) * kRowPad + kE] = 0;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nnzb; b += (int64_t)gridDim.x * 4) {
+    const double* v = values + b * (kE * kE);
+#pragma unroll
+    for (int u = 0; u < (kE * kE + 63) / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kE * kE) {
+        const double x = v[e];
+        const int r = e / kE, c = e - r * kE;  // the block's row r, column c
+        const int pos = transpose ? c * kRowPad + r : r * kRowPad + c;
+        const uint16_t h0 = bf16_bits((float)x);
+        const double r1 = x - bf16_value(h0);
+        const uint16_t h1 = bf16_bits((float)r1);
+        const double r2 = r1 - bf16_value(h1);
+        t[pos] = h0;
+        t[kSlice + pos] = h1;
+        t[2 * kSlice + pos] = bf16_bits((float)r2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    u32x4* const o = reinterpret_cast<u32x4*>(out + b * kSplitBlock);
+    const u32x4* const src = reinterpret_cast<const u32x4*>(t);
+    for (int x = lane; x < kChunks; x += 64) o[x] = src[x];
+    // every lane has read the tile before the next block overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
-
 
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -311,8 +331,8 @@ int64_t split_elems(int64_t nblocks) { return nblocks * kSplitBlock; }
 hipError_t launch_split_bf16x3(const double* values, const int64_t* d_nnzb, int64_t bound, int transpose,
                                uint16_t* out, hipStream_t s) {
   if (bound <= 0) return hipSuccess;
-  int64_t blocks = (bound * kSlice + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  int64_t blocks = (bound + 3) / 4;  // one wave per block
+  if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_split_bf16x3, dim3((uint32_t)blocks), dim3(256), 0, s, values, d_nnzb, transpose, out);
   return hipGetLastError();
 }
