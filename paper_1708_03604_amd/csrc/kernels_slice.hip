@@ -73,57 +73,89 @@ __global__ void k_block_rows(const int32_t* __restrict__ row_ptr, int32_t nbrows
     for (int32_t b = row_ptr[i]; b < row_ptr[i + 1]; ++b) rowof[b] = i;
 }
 
-// Scale exponents: one wave per block; lane R < 23 takes the largest |value|
-// of row R (A) or column R (B, transpose = 1) and raises exps[grp[b]*23 + R].
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Scale exponents: one wave per block.  The lanes read the block's values
+// contiguously and raise, in LDS, the frexp exponent of each row's (A) or
+// column's (B, transpose = 1) nonzero values (the exponent of the largest
+// magnitude is the largest exponent); lane R < 23 then raises
+// exps[grp[b]*23 + R] with it.
 template <int TRANSPOSE>
 __global__ __launch_bounds__(256) void k_slice_exponents(const double* __restrict__ values,
                                                          const int64_t* __restrict__ d_nnzb,
                                                          const int32_t* __restrict__ grp, int32_t* __restrict__ exps) {
+  __shared__ int32_t emax[4][kE];
   const int64_t nnzb = *d_nnzb;
-  const int lane = threadIdx.x & 63;
-  for (int64_t b = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; b < nnzb; b += (int64_t)gridDim.x * 4) {
-    if (lane >= kE) continue;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nnzb; b += (int64_t)gridDim.x * 4) {
+    if (lane < kE) emax[wv][lane] = INT_MIN;
+    wave_sync();
     const double* v = values + b * kNE;
-    double m = 0.0;
 #pragma unroll
-    for (int c = 0; c < kE; ++c) m = fmax(m, fabs(TRANSPOSE ? v[c * kE + lane] : v[lane * kE + c]));
-    if (m > 0.0) {
-      int e;
-      (void)frexp(m, &e);
-      atomicMax(&exps[(int64_t)grp[b] * kE + lane], e);
+    for (int u = 0; u < (kNE + 63) / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kNE) {
+        const double x = v[e];
+        if (x != 0.0) {
+          const int r = e / kE, c = e - r * kE;
+          int ex;
+          (void)frexp(x, &ex);
+          atomicMax(&emax[wv][TRANSPOSE ? c : r], ex);
+        }
+      }
     }
+    wave_sync();
+    if (lane < kE) {
+      const int32_t ex = emax[wv][lane];
+      if (ex != INT_MIN) atomicMax(&exps[(int64_t)grp[b] * kE + lane], ex);
+    }
+    wave_sync();
   }
 }
 
-// Digits of every value: one workgroup per block (grid-stride).  The block's
-// 3872 bytes are assembled in LDS and stored as 16-byte pieces.
+// Digits of every value: one wave per block.  The lanes read the block's
+// values contiguously, write the seven digits of each into the block's
+// 3872-byte layout in LDS (pad bytes zeroed once, never written), and store
+// the block as 16-byte pieces.
 template <int TRANSPOSE>
 __global__ __launch_bounds__(256) void k_slice_int8(const double* __restrict__ values, const int64_t* __restrict__ d_nnzb,
                                                     const int32_t* __restrict__ grp, const int32_t* __restrict__ exps,
                                                     uint8_t* __restrict__ out) {
-  __shared__ __align__(16) int8_t buf[kBlockBytes];
+  __shared__ __align__(16) int8_t buf[4][kBlockBytes];
   const int64_t nnzb = *d_nnzb;
-  for (int64_t b = blockIdx.x; b < nnzb; b += gridDim.x) {
-    for (int x = threadIdx.x; x < kChunks; x += 256) reinterpret_cast<uint4*>(buf)[x] = make_uint4(0, 0, 0, 0);
-    __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int8_t* const t = buf[wv];
+  for (int x = lane; x < kChunks; x += 64) reinterpret_cast<uint4*>(t)[x] = make_uint4(0, 0, 0, 0);
+  wave_sync();
+  for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nnzb; b += (int64_t)gridDim.x * 4) {
     const int32_t gb = grp[b];
-    for (int t = threadIdx.x; t < kNE; t += 256) {
-      const int r = t / kE, c = t - r * kE;        // stored position
-      const int R = TRANSPOSE ? c : r, C = TRANSPOSE ? r : c;  // slice row, position in the slice
-      const int32_t e = exps[(int64_t)gb * kE + R];
-      const double y = e == INT_MIN ? 0.0 : ldexp(values[b * kNE + t], -e);
-      double v = 64.0 * y;
-      for (int s = 0; s < kSlices; ++s) {
-        const double d = rint(v);
-        const int pos = TRANSPOSE ? kSlices - 1 - s : s;
-        buf[R * kRowBytes + pos * kSliceBytes + C] = (int8_t)(int)d;
-        v = 128.0 * (v - d);
+    const double* v = values + b * kNE;
+#pragma unroll
+    for (int u = 0; u < (kNE + 63) / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < kNE) {
+        const int r = e / kE, c = e - r * kE;                    // stored position
+        const int R = TRANSPOSE ? c : r, C = TRANSPOSE ? r : c;  // slice row, position in the slice
+        const int32_t ex = exps[(int64_t)gb * kE + R];
+        const double y = ex == INT_MIN ? 0.0 : ldexp(v[e], -ex);
+        double w = 64.0 * y;
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) {
+          const double d = rint(w);
+          const int pos = TRANSPOSE ? kSlices - 1 - sl : sl;
+          t[R * kRowBytes + pos * kSliceBytes + C] = (int8_t)(int)d;
+          w = 128.0 * (w - d);
+        }
       }
     }
-    __syncthreads();
-    uint4* o = reinterpret_cast<uint4*>(out + b * kBlockBytes);
-    for (int x = threadIdx.x; x < kChunks; x += 256) o[x] = reinterpret_cast<const uint4*>(buf)[x];
-    __syncthreads();
+    wave_sync();
+    uint4* const o = reinterpret_cast<uint4*>(out + b * kBlockBytes);
+    for (int x = lane; x < kChunks; x += 64) o[x] = reinterpret_cast<const uint4*>(t)[x];
+    wave_sync();
   }
 }
 
@@ -364,8 +396,8 @@ hipError_t launch_slice_int8x7(const double* values, const int64_t* d_nnzb, int6
     hipLaunchKernelGGL(k_block_rows, dim3(g), dim3(256), 0, s, row_ptr, nbrows, rowof);
     grp = rowof;
   }
-  const int64_t ge = std::min<int64_t>((bound + 3) / 4, 65536);
-  const int64_t gs = std::min<int64_t>(bound, 65536);
+  const int64_t ge = std::min<int64_t>((bound + 3) / 4, 16384);  // one wave per block
+  const int64_t gs = ge;
   if (transpose) {
     hipLaunchKernelGGL(k_slice_exponents<1>, dim3((uint32_t)ge), dim3(256), 0, s, values, d_nnzb, grp, exps);
     hipLaunchKernelGGL(k_slice_int8<1>, dim3((uint32_t)gs), dim3(256), 0, s, values, d_nnzb, grp, exps, out);
