@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1708_03604_amd import bsmm
 from paper_1708_03604_amd import workloads as W
-from test_gpu_parity import check, gpu_multiply, sampled_rows_check
+from test_gpu_parity import check, gpu_multiply
 
 pytestmark = pytest.mark.gpu
 
@@ -33,21 +33,20 @@ def test_semi_empirical_small_full():
     check(oracle.multiply(w.alpha, w.A, w.B, w.beta, None, w.eps), got)
 
 
-def test_semi_empirical_full_size_sampled_rows():
+def test_semi_empirical_full_size():
+    # the S-E-shaped workload at full size, every row: 234 M products, the
+    # oracle's share is about 13 s on 16 host threads
     w = W.semi_empirical()
     got = gpu_multiply(w.A, w.B, None, w.alpha, w.beta, w.eps)
-    nb = np.diff(w.A.row_ptr)
-    rows = sorted({0, w.A.nbrows - 1, int(np.argmax(nb)), int(np.argmin(nb))}
-                  | set(np.random.default_rng(9).choice(w.A.nbrows, 12, replace=False).tolist()))
-    sampled_rows_check(w, rows, got)
     print(f"S-E: {got[4]['candidates']} candidates, {got[4]['products']} products, {got[4]['nnzb']} C blocks")
+    check(oracle.multiply(w.alpha, w.A, w.B, w.beta, None, w.eps), got)
 
 
-def test_mixed_dense_sampled_rows():
+def test_mixed_dense_full_size():
     w = W.mixed_dense()
     got = gpu_multiply(w.A, w.B, w.C_old, w.alpha, w.beta, w.eps)
     assert got[4]["products"] == 64 ** 3 and got[4]["nnzb"] == 64 * 64
-    sampled_rows_check(w, [0, 1, 2, 31, 62, 63], got)
+    check(oracle.multiply(w.alpha, w.A, w.B, w.beta, w.C_old, w.eps), got)
 
 
 def test_mixed_dense_small_full():
