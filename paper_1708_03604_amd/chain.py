@@ -80,11 +80,15 @@ class SignChain:
         bsmm.bsmm_frobenius(self.R.handle, self.residual, st)
         self.final = cur
 
-    def count_flops(self, progress=None):
+    def count_flops(self, progress=None, after_multiply=None):
         """Run the chain eagerly, reading each multiply's counters (one host
         synchronisation per multiply); returns (useful flops of the whole
         chain, kept products, list of result block counts per step).
-        progress(step, blocks), if given, is called after every step."""
+        progress(step, blocks), if given, is called after every step;
+        after_multiply(step, args), if given, after every multiply and before
+        its result is filtered, with args = (alpha, A, B, beta, C_in, C,
+        filter_eps) as the multiply received them (step = self.steps for the
+        residual multiply)."""
         st = self.stream
         cur = self.X0
         flops, prods, blocks = 0.0, 0, []
@@ -95,12 +99,16 @@ class SignChain:
                 s = bsmm.bsmm_stats(args[5].handle)
                 flops += s["useful_flops"]
                 prods += s["products"]
+                if after_multiply is not None:
+                    after_multiply(k, args + (self.eps,))
                 bsmm.bsmm_filter(args[5].handle, self.eps, st)
             blocks.append(nxt.info()[2])
             if progress is not None:
                 progress(k, blocks[-1])
             cur = nxt
         bsmm.multiply(1.0, cur, cur, -1.0, self.I1, self.R, 0.0, stream=st)
+        if after_multiply is not None:
+            after_multiply(self.steps, (1.0, cur, cur, -1.0, self.I1, self.R, 0.0))
         s = bsmm.bsmm_stats(self.R.handle)
         flops += s["useful_flops"]
         prods += s["products"]
