@@ -108,6 +108,7 @@ struct bsmm_matrix {
   int32_t nnzb = 0;
   int64_t nvals = 0;
   int uniform = 0;  // common block edge if every row and column size is equal, else 0
+  int col_uniform = 0;  // common block edge of the columns, else 0
   int max_edge = 0; // largest row or column block size
   uint32_t row_edges = 0, col_edges = 0;  // bit e-1 set for each block edge e (edges above 32 set bit 31)
   Storage cur, spare;
@@ -388,6 +389,10 @@ bsmm_status bsmm_create(bsmm_mat* out, int32_t nbrows, int32_t nbcols, const int
   for (int32_t j = 0; j < nbcols && u; ++j)
     if (col_sizes[j] != u) u = 0;
   m->uniform = u;
+  int cu = nbcols > 0 ? col_sizes[0] : 0;
+  for (int32_t j = 0; j < nbcols && cu; ++j)
+    if (col_sizes[j] != cu) cu = 0;
+  m->col_uniform = cu;
   for (int32_t i = 0; i < nbrows; ++i) m->max_edge = std::max(m->max_edge, row_sizes[i]);
   for (int32_t j = 0; j < nbcols; ++j) m->max_edge = std::max(m->max_edge, col_sizes[j]);
   for (int32_t i = 0; i < nbrows; ++i) m->row_edges |= 1u << (std::min(row_sizes[i], 32) - 1);
@@ -677,6 +682,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.normB = normB;
   g.c_row_sizes = C->d_row_sizes.p;
   g.c_col_sizes = C->d_col_sizes.p;
+  g.c_col_uniform = C->col_uniform;
   g.row_nc = C->rows[0].p;
   g.row_np = C->rows[1].p;
   g.row_nv = C->rows[2].p;

@@ -71,6 +71,7 @@ struct SymArgs {
   const double* normB;  // [B.nnzb] (only if use_eps)
   const int32_t* c_row_sizes;
   const int32_t* c_col_sizes;
+  int32_t c_col_uniform;  // common size of every block column of C, or 0 (then c_col_sizes is read)
   // count pass outputs (length nbrows+1; entry i+1 written for row i)
   int64_t* row_nc;
   int64_t* row_np;

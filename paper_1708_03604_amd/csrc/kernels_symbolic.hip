@@ -24,6 +24,12 @@ static_assert(kLargeRowA % kSymThreads == 0 && kMaxRowA % kSymThreads == 0, "A c
 static_assert(kLargeRowBlocks % kSymThreads == 0 && kMaxRowBlocks % kSymThreads == 0, "row chunking");
 static_assert(2 * kLargeRowBlocks <= kHashSlots && 2 * kMaxRowBlocks <= (1 << kHugeHashBits), "hash load");
 
+// Size of C's block column j (a kernel argument when every column has it:
+// no gather per candidate).
+__device__ __forceinline__ int32_t col_size(const SymArgs& g, int32_t j) {
+  return g.c_col_uniform ? g.c_col_uniform : g.c_col_sizes[j];
+}
+
 // Rows of the current fill panel, and the stack position its index 0 holds.
 __device__ __forceinline__ bool in_panel(const SymArgs& g, int32_t i) {
   return !g.panel || (i >= g.panel[0] && i < g.panel[1]);
@@ -180,6 +186,18 @@ __device__ __forceinline__ bool keep_product(const SymArgs& g, const RowA<RA>& r
 // flight per thread (rows of thousands of candidates are latency-bound).
 constexpr int kCandBatch = 4;
 
+// Candidates [lo, hi) of a row pass, one contiguous segment per wave: lanes
+// take consecutive candidates (coalesced loads) and a lane's next candidate is
+// 64 further on, usually in the same or the next A entry, so the entry lookup
+// from the previous one rarely needs its binary search.
+constexpr int kSymWaves = kSymThreads / 64;
+__device__ __forceinline__ void wave_segment(int32_t lo, int32_t hi, int32_t* s0, int32_t* s1) {
+  const int32_t seg = ((hi - lo + kSymWaves * 64 - 1) / (kSymWaves * 64)) * 64;
+  const int32_t w = (int32_t)(threadIdx.x >> 6);
+  *s0 = min(hi, lo + w * seg);
+  *s1 = min(hi, *s0 + seg);
+}
+
 // LDS of one workgroup of the count pass.  The hash always has the form's
 // full size (the row's distinct columns are what the pass counts); the A
 // entries of the row take RA slots.
@@ -236,32 +254,34 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
     uint32_t np = 0;
     uint64_t nf = 0;
     int32_t hint = 0;  // A entry of this thread's last candidate
+    int32_t s0, s1;
+    wave_segment(0, T, &s0, &s1);
     // kCandBatch candidates per thread at a time, their global loads issued together
-    for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
+    for (int32_t tb = s0 + (tid & 63); tb < s1; tb += kCandBatch * 64) {
       int32_t pp[kCandBatch], jj[kCandBatch];
       bool kk[kCandBatch];
 #pragma unroll
       for (int u = 0; u < kCandBatch; ++u) {
-        const int32_t t = tb + u * kSymThreads;
+        const int32_t t = tb + u * 64;
         int32_t p = 0, q = 0;
-        if (t < T) candidate(ra, nA, t, &hint, &p, &q);
+        if (t < s1) candidate(ra, nA, t, &hint, &p, &q);
         pp[u] = p;
-        kk[u] = t < T && keep_product(g, ra, p, q);
-        jj[u] = t < T ? g.B.col_idx[q] : 0;
+        kk[u] = t < s1 && keep_product(g, ra, p, q);
+        jj[u] = t < s1 ? g.B.col_idx[q] : 0;
       }
 #pragma unroll
       for (int u = 0; u < kCandBatch; ++u) {
         if (!kk[u]) continue;
         ++np;
         const int32_t j = jj[u];
-        nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)ra.ks[pp[u]];
+        nf += (uint64_t)col_size(g, j) * (uint64_t)ra.ks[pp[u]];
         bool fresh;
         const int h = hash_insert<HB>(hkey, j, &fresh);
         if (h < 0) {
           s_bad = 1;
         } else if (fresh) {
           atomicAdd(&s_nc, 1);
-          atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+          atomicAdd(&s_sumn, (unsigned long long)col_size(g, j));
         }
       }
     }
@@ -275,7 +295,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
           s_bad = 1;
         } else if (fresh) {
           atomicAdd(&s_nc, 1);
-          atomicAdd(&s_sumn, (unsigned long long)g.c_col_sizes[j]);
+          atomicAdd(&s_sumn, (unsigned long long)col_size(g, j));
         }
       }
     }
@@ -401,7 +421,7 @@ __device__ bool thin_load(const SymArgs& g, int32_t i, ThinRow& r) {
           }
         }
         ++r.n;
-        r.nf += (uint64_t)g.c_col_sizes[j] * (uint64_t)thin_sel(ks, p);
+        r.nf += (uint64_t)col_size(g, j) * (uint64_t)thin_sel(ks, p);
       }
     }
   }
@@ -431,7 +451,7 @@ __global__ __launch_bounds__(256) void k_sym_count_thin(SymArgs g) {
   int64_t sumn = 0;
 #pragma unroll
   for (int x = 0; x < kThinC; ++x)
-    if (x < r.nc) sumn += g.c_col_sizes[r.col[x]];
+    if (x < r.nc) sumn += col_size(g, r.col[x]);
   const int64_t m = g.c_row_sizes[i];
   g.row_nc[i] = r.nc;
   g.row_np[i] = r.n;
@@ -478,7 +498,7 @@ __global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
           ++pc;
         }
       }
-      vc += g.c_col_sizes[j];
+      vc += col_size(g, j);
     }
   }
 }
@@ -687,27 +707,29 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
     if (T < 0) return;  // uniform over the workgroup; reported by the count pass
     const bool one_chunk = T <= kCandCacheF;
     int32_t hint = 0;  // A entry of this thread's last candidate
-    for (int32_t tb = tid; tb < T; tb += kCandBatch * kSymThreads) {
+    int32_t s0, s1;
+    wave_segment(0, T, &s0, &s1);
+    for (int32_t tb = s0 + (tid & 63); tb < s1; tb += kCandBatch * 64) {
       int32_t jj[kCandBatch];
       bool kk[kCandBatch];
 #pragma unroll
       for (int u = 0; u < kCandBatch; ++u) {
-        const int32_t t = tb + u * kSymThreads;
-        const int32_t p = t < T ? (hint = fill_entry_from(ra, nA, hint, t)) : 0;
+        const int32_t t = tb + u * 64;
+        const int32_t p = t < s1 ? (hint = fill_entry_from(ra, nA, hint, t)) : 0;
         const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-        kk[u] = t < T && fill_keep(g, ra, p, q);
-        jj[u] = t < T ? g.B.col_idx[q] : 0;
+        kk[u] = t < s1 && fill_keep(g, ra, p, q);
+        jj[u] = t < s1 ? g.B.col_idx[q] : 0;
       }
 #pragma unroll
       for (int u = 0; u < kCandBatch; ++u) {
-        const int32_t t = tb + u * kSymThreads;
+        const int32_t t = tb + u * 64;
         int h = -1;
         if (kk[u]) {
           bool fresh;
           h = hash_insert<kHashBitsF>(hkey, jj[u], &fresh);
           if (h >= 0) atomicAdd(&hcnt[h], 1);
         }
-        if (one_chunk && t < T) cslot[t] = (int16_t)h;
+        if (one_chunk && t < s1) cslot[t] = (int16_t)h;
       }
     }
     if (g.use_old) {
@@ -741,7 +763,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
       const int h = eslot[e];
       spre[r] = hcnt[h];
       hcnt[h] = r;
-      svs[r] = g.c_col_sizes[key];
+      svs[r] = col_size(g, key);
       g.c_col_idx[crow + r] = key;
       g.c_old_idx[crow + r] = hold[h];
     }
@@ -787,21 +809,23 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
     for (int32_t t0 = 0; t0 < T; t0 += kCandCacheF) {
       const int32_t t1 = T - t0 > kCandCacheF ? t0 + kCandCacheF : T;
       if (!one_chunk) {
-        for (int32_t tb = t0 + tid; tb < t1; tb += kCandBatch * kSymThreads) {
+        int32_t c0, c1;
+        wave_segment(t0, t1, &c0, &c1);
+        for (int32_t tb = c0 + (tid & 63); tb < c1; tb += kCandBatch * 64) {
           int32_t jj[kCandBatch];
           bool kk[kCandBatch];
 #pragma unroll
           for (int u = 0; u < kCandBatch; ++u) {
-            const int32_t t = tb + u * kSymThreads;
-            const int32_t p = t < t1 ? (chint = fill_entry_from(ra, nA, chint, t)) : 0;
+            const int32_t t = tb + u * 64;
+            const int32_t p = t < c1 ? (chint = fill_entry_from(ra, nA, chint, t)) : 0;
             const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-            kk[u] = t < t1 && fill_keep(g, ra, p, q);
-            jj[u] = t < t1 ? g.B.col_idx[q] : 0;
+            kk[u] = t < c1 && fill_keep(g, ra, p, q);
+            jj[u] = t < c1 ? g.B.col_idx[q] : 0;
           }
 #pragma unroll
           for (int u = 0; u < kCandBatch; ++u) {
-            const int32_t t = tb + u * kSymThreads;
-            if (t < t1) cslot[t - t0] = (int16_t)(kk[u] ? hash_find<kHashBitsF>(hkey, jj[u]) : -1);
+            const int32_t t = tb + u * 64;
+            if (t < c1) cslot[t - t0] = (int16_t)(kk[u] ? hash_find<kHashBitsF>(hkey, jj[u]) : -1);
           }
         }
         __syncthreads();
@@ -817,15 +841,17 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
         const int32_t r1 = r0 + 32 <= pl + 1 ? r0 + 32 : pl + 1;
         const int32_t tb = ra.pre[r0] > t0 ? ra.pre[r0] : t0;
         const int32_t te = ra.pre[r1] < t1 ? ra.pre[r1] : t1;
+        int32_t w0, w1;
+        wave_segment(tb, te, &w0, &w1);
         int32_t rh = r0;  // pre[r0] <= tb: a valid hint for every candidate of the round
-        for (int32_t t = tb + tid; t < te; t += kSymThreads) {
+        for (int32_t t = w0 + (tid & 63); t < w1; t += 64) {
           const int h = cslot[t - t0];
           rh = fill_entry_from(ra, nA, rh, t);
           if (h >= 0) atomicOr(&rmask[hcnt[h]], 1u << (rh - r0));
         }
         __syncthreads();
         rh = r0;
-        for (int32_t t = tb + tid; t < te; t += kSymThreads) {
+        for (int32_t t = w0 + (tid & 63); t < w1; t += 64) {
           const int h = cslot[t - t0];
           rh = fill_entry_from(ra, nA, rh, t);
           if (h >= 0) {
