@@ -842,6 +842,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.prod_b = C->prod_b.p;
   na.c_values = out.values.p;
   na.wide_inner = (A->col_edges & 0x7fffu) == 0;  // no inner block edge below 16
+  na.uniform = uniform;
   na.c_row_ptr = out.row_ptr.p;
   ClassVariants variants{-1, -1, -1, -1};
   // One pass per stack panel: fill the panel's rows (pattern and products),

@@ -119,6 +119,7 @@ struct NumArgs {
   const int32_t* prod_b;
   double* c_values;
   int wide_inner;          // every inner block edge >= 16: the generic path may use the matrix-core form
+  int uniform;             // common edge of every block of A and B, or 0
   // 23x23 paths: only the C blocks of rows [panel[0], panel[1]) are computed,
   // and prod_a/prod_b hold that panel's products from index 0; nullptr = all
   const int32_t* panel;

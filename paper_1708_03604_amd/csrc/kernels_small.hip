@@ -192,13 +192,16 @@ __global__ __launch_bounds__(kClassThreads) void k_class_scatter(
 // products from stack position p0), desc[qstart[e] + l] = {A value offset
 // | k << 56, B value offset} of its l-th product.  A wave serves four
 // entries at a time, 16 lanes each (a C block has about a dozen products).
+// With every block of A and B of edge ue (> 0) the offsets are the block
+// indices times ue^2, without gathering the offset tables.
 __global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ totals,
                                                     const int4* __restrict__ list,
                                                     const int64_t* __restrict__ qstart,
                                                     const int32_t* __restrict__ prod_a,
                                                     const int32_t* __restrict__ prod_b,
                                                     const int64_t* __restrict__ Aoff,
-                                                    const int64_t* __restrict__ Boff, int4* __restrict__ desc) {
+                                                    const int64_t* __restrict__ Boff, int32_t ue,
+                                                    int4* __restrict__ desc) {
   const int32_t nnzc = live_nnzc(totals);
   const int lane = threadIdx.x & 63, g = lane >> 4, l0 = lane & 15;
   const int32_t nwaves = gridDim.x * 4;
@@ -215,9 +218,17 @@ __global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ 
     for (int32_t l = l0; l < ent.z; l += 16) {
       const int64_t p = (int64_t)ent.y + l;
       const int32_t a = prod_a[p], b = prod_b[p];
-      const int64_t ao = Aoff[a];
-      const int32_t k = (int32_t)(((uint32_t)(Aoff[a + 1] - ao) * inv) >> 16);
-      const int64_t bo = Boff[b];
+      int64_t ao, bo;
+      int32_t k;
+      if (ue) {
+        ao = (int64_t)a * (ue * ue);
+        bo = (int64_t)b * (ue * ue);
+        k = ue;
+      } else {
+        ao = Aoff[a];
+        k = (int32_t)(((uint32_t)(Aoff[a + 1] - ao) * inv) >> 16);
+        bo = Boff[b];
+      }
       desc[q + l] = make_int4((int32_t)(uint32_t)ao, (int32_t)((uint32_t)(ao >> 32) | ((uint32_t)k << 24)),
                               (int32_t)(uint32_t)bo, (int32_t)(uint32_t)(bo >> 32));
     }
@@ -1234,7 +1245,7 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
   int64_t blocks = (a.nnzc_bound + 15) / 16;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_class_desc, dim3((uint32_t)blocks), dim3(256), 0, s, a.totals, list, qstart, a.prod_a,
-                     a.prod_b, a.A.blk_off, a.B.blk_off, desc);
+                     a.prod_b, a.A.blk_off, a.B.blk_off, (int32_t)a.uniform, desc);
   return hipGetLastError();
 }
 
