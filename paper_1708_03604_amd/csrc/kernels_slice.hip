@@ -80,38 +80,35 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Scale exponents: one wave per block.  The lanes read the block's values
-// contiguously and raise, in LDS, the frexp exponent of each row's (A) or
-// column's (B, transpose = 1) nonzero values (the exponent of the largest
-// magnitude is the largest exponent); lane R < 23 then raises
-// exps[grp[b]*23 + R] with it.
+// contiguously and put each value's frexp exponent (INT_MIN for zero) in the
+// wave's LDS table; lane R < 23 then takes the largest over row R (A) or
+// column R (B, transpose = 1) -- the exponent of the largest magnitude -- and
+// raises exps[grp[b]*23 + R] with it.
 template <int TRANSPOSE>
 __global__ __launch_bounds__(256) void k_slice_exponents(const double* __restrict__ values,
                                                          const int64_t* __restrict__ d_nnzb,
                                                          const int32_t* __restrict__ grp, int32_t* __restrict__ exps) {
-  __shared__ int32_t emax[4][kE];
+  __shared__ int32_t ext[4][kNE];
   const int64_t nnzb = *d_nnzb;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int64_t b = (int64_t)blockIdx.x * 4 + wv; b < nnzb; b += (int64_t)gridDim.x * 4) {
-    if (lane < kE) emax[wv][lane] = INT_MIN;
-    wave_sync();
     const double* v = values + b * kNE;
 #pragma unroll
     for (int u = 0; u < (kNE + 63) / 64; ++u) {
       const int e = lane + 64 * u;
       if (e < kNE) {
         const double x = v[e];
-        if (x != 0.0) {
-          const int r = e / kE, c = e - r * kE;
-          int ex;
-          (void)frexp(x, &ex);
-          atomicMax(&emax[wv][TRANSPOSE ? c : r], ex);
-        }
+        int ex = INT_MIN;
+        if (x != 0.0) (void)frexp(x, &ex);
+        ext[wv][e] = ex;
       }
     }
     wave_sync();
     if (lane < kE) {
-      const int32_t ex = emax[wv][lane];
-      if (ex != INT_MIN) atomicMax(&exps[(int64_t)grp[b] * kE + lane], ex);
+      int32_t m = INT_MIN;
+#pragma unroll
+      for (int c = 0; c < kE; ++c) m = max(m, ext[wv][TRANSPOSE ? c * kE + lane : lane * kE + c]);
+      if (m != INT_MIN) atomicMax(&exps[(int64_t)grp[b] * kE + lane], m);
     }
     wave_sync();
   }
