@@ -308,16 +308,20 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     if (p == pe && !advance()) break;
     asm volatile("; slot 0");
     wsync();
+    __builtin_amdgcn_s_setprio(1);  // as in the FP64 kernel: staging and loads first
     stage_write(opa0, opb0);
     fetch_next(opa0, opb0);
+    __builtin_amdgcn_s_setprio(0);
     wsync();
     multiply_stage();
     ++p;
     if (p == pe && !advance()) break;
     asm volatile("; slot 1");
     wsync();
+    __builtin_amdgcn_s_setprio(1);  // as in the FP64 kernel: staging and loads first
     stage_write(opa1, opb1);
     fetch_next(opa1, opb1);
+    __builtin_amdgcn_s_setprio(0);
     wsync();
     multiply_stage();
     ++p;
