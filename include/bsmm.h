@@ -308,10 +308,12 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
  * stack panel of a multiply into m may hold, 2 .. 2^31-1, default 2^30 (8 GB
  * of indices).  A multiply of uniform 23x23 blocks (any precision) with more
  * products than the limit builds and consumes its stack in panels of
- * consecutive C block rows, each holding at most the limit (a panel starts
- * at every multiple of half the limit, so a block row may hold at most half
- * of it: BSMM_E_CAPACITY otherwise).  Results are bit-identical to the
- * whole-stack multiply.  Other block sizes build the whole stack (at most
+ * consecutive C block rows, each holding at most the limit: with R the most
+ * products of one block row, a panel starts at every multiple of
+ * max(limit - R, limit/2) products, so panels are nearly full, and a block
+ * row may hold at most half the limit (BSMM_E_CAPACITY otherwise).  Results
+ * are bit-identical to the whole-stack multiply; the multiply's stats count
+ * the panels that hold a row.  Other block sizes build the whole stack (at most
  * 2^31-1 products) whatever the limit.  For a reserved output the limit sizes
  * the stack: bsmm_reserve allocates min(max_products, limit) entries and the
  * multiplies run ceil(max_products / (limit/2)) + 1 panels (at most 4096;

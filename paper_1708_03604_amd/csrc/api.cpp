@@ -712,6 +712,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // (at most stack_limit products each); the other paths build it whole.
   const bool panel_ok = uniform == 23;
   int32_t npanels = 1;
+  int32_t used_panels = 0;  // eager multiplies: the panels that hold a row (the rest are empty)
   int64_t nnzc = 0, nprod = 0, nvals = 0, ncand = 0, nflop_half = 0;
   int64_t nnzc_bound, nprod_bound, nvals_bound, stack_bound;
   if (reserved) {
@@ -751,7 +752,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       if (C->panels.ensure(npanels + 1) != hipSuccess) return fail(BSMM_E_NOMEM, "scratch allocation failed");
       HIP_TRY(launch_panel_rows(C->pre[1].p, nbrows, std::max<int64_t>(C->stack_limit / 2, 1), npanels,
                                 C->stack_limit, C->panels.p, C->totals.p, s));
-      HIP_TRY(hipMemcpyAsync(C->h_totals + kTotCount, C->totals.p + kTotPanelMax, sizeof(int64_t),
+      HIP_TRY(hipMemcpyAsync(C->h_totals + kTotCount, C->totals.p + kTotPanelMax, 2 * sizeof(int64_t),
                              hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       if (C->h_totals[kTotCount] > C->stack_limit)
@@ -760,6 +761,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
                                          std::to_string(C->stack_limit) +
                                          " (a block row holds more than half of it; bsmm_set_stack_limit)");
       stack_bound = C->stack_limit;
+      used_panels = (int32_t)C->h_totals[kTotCount + 1];
     } else if (nprod > 0x7fffffffLL) {
       return fail(BSMM_E_CAPACITY, "more than 2^31-1 block products");
     }
@@ -885,7 +887,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   if (in_place) std::swap(C->cur, C->spare);
   C->has_stack = npanels == 1;
   C->stack_panelled = npanels > 1;
-  C->stats.panels = npanels;
+  C->stats.panels = used_panels > 0 ? used_panels : npanels;
   C->stats.path = split ? BSMM_PATH_SPLIT23 : slice ? BSMM_PATH_SLICE23 : small ? BSMM_PATH_SMALL : uniform == 23 ? BSMM_PATH_TILE23 : BSMM_PATH_GENERIC;
   std::copy(variants.begin(), variants.end(), C->stats.variants);
   if (reserved) return BSMM_OK;

@@ -49,7 +49,8 @@ enum : int {
   kTotFlopHalf = 5,  // sum over kept products of m*n*k
   kTotAbort = 6,     // nonzero: the result does not fit; later kernels do nothing
   kTotPanelMax = 7,  // most products of any stack panel (panelled multiplies)
-  kTotCount = 8
+  kTotPanelUsed = 8, // stack panels that hold a block row (panelled multiplies)
+  kTotCount = 9
 };
 
 // Doubles of zero slack kept after the last value of every matrix: the
@@ -141,9 +142,12 @@ hipError_t launch_finish_multiply(const int64_t* totals, double* values, int64_t
 hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_nvals, int64_t cap_nprod,
                                  int big_stack, hipStream_t s);
 // Stacks in panels of rows (23x23 paths): panels[0..np] row bounds from the
-// per-row product prefix np_pre, each panel starting at a multiple of half
-// products; the largest panel's products go to totals[kTotPanelMax], and the
-// multiply is aborted if they exceed cap.  np <= kMaxPanels.
+// per-row product prefix np_pre, each panel starting at a multiple of
+// max(cap - R, half) products (R: the most products of one row), so that no
+// panel exceeds cap while R <= cap - half; the largest panel's products go to
+// totals[kTotPanelMax] (the multiply is aborted if they exceed cap), the count
+// of panels that hold a row to totals[kTotPanelUsed].  Panels past the last
+// row are empty.  np <= kMaxPanels.
 constexpr int32_t kMaxPanels = 4096;
 hipError_t launch_panel_rows(const int64_t* np_pre, int32_t nbrows, int64_t half, int32_t np, int64_t cap,
                              int32_t* panels, int64_t* totals, hipStream_t s);

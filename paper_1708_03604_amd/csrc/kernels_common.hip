@@ -4,6 +4,7 @@
 // paper): lane l of a wave sums x_e^2 for e = l, l+64, ... with fused
 // multiply-add, then partial l += partial l+d for d = 32..1, then a correctly
 // rounded square root.
+#include "block_scan.h"
 #include "bsmm_internal.h"
 
 namespace bsmm {
@@ -101,28 +102,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;
 
-// Exclusive scan of v over the workgroup; *total gets the workgroup sum.
-__device__ int64_t wg_exclusive_scan(int64_t v, int64_t* total) {
-  __shared__ int64_t wsum[kScanThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int64_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[wave] = x;
-  __syncthreads();
-  int64_t off = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kScanThreads / 64; ++w) {
-    if (w < wave) off += wsum[w];
-    tot += wsum[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + x - v;
-}
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_partial(const int64_t* __restrict__ in, int64_t n,
                                                                int64_t* __restrict__ partial) {
@@ -134,7 +113,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partial(const int64_t* __
     if (i < n) s += in[i];
   }
   int64_t tot;
-  wg_exclusive_scan(s, &tot);
+  block_exclusive_scan<kScanThreads>(s, &tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
@@ -145,7 +124,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t* __restr
     const int64_t i = base + threadIdx.x;
     const int64_t v = i < nchunks ? partial[i] : 0;
     int64_t tot;
-    const int64_t ex = wg_exclusive_scan(v, &tot);
+    const int64_t ex = block_exclusive_scan<kScanThreads>(v, &tot);
     if (i < nchunks) partial[i] = carry + ex;
     carry += tot;
   }
@@ -165,7 +144,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const int64_t* __re
     s += v[u];
   }
   int64_t tot;
-  int64_t run = partial[blockIdx.x] + wg_exclusive_scan(s, &tot);
+  int64_t run = partial[blockIdx.x] + block_exclusive_scan<kScanThreads>(s, &tot);
 #pragma unroll
   for (int u = 0; u < kScanItems; ++u) {
     if (base + u < n) out[base + u] = run;
@@ -301,24 +280,44 @@ hipError_t launch_check_capacity(int64_t* totals, int64_t cap_nnzb, int64_t cap_
 
 // ---------------------------------------------------------------- stack panels
 
-// Row panels of a stack built and consumed in parts: panel p is rows
-// [panels[p], panels[p+1]) with panels[p] the first row whose products start
-// at or after p*half (np_pre: exclusive prefix of the per-row product
-// counts), panels[np] = nbrows.  A panel then holds at most half plus one
-// row's products.  totals[kTotPanelMax] receives the most products of any
-// panel; above cap the multiply is aborted (later kernels do nothing).
+// Row panels of a stack built and consumed in parts.  With R the most
+// products of one block row, panel starts lie w = max(cap - R, half) products
+// apart: panel p is rows [panels[p], panels[p+1]) with panels[p] the first row
+// whose products start at or after p*w (np_pre: exclusive prefix of the
+// per-row product counts), panels[np] = nbrows.  A panel then holds at most
+// w + R products, which is cap whenever R <= cap - half, so a panel is as
+// full as the limit allows and the fill of its rows has as many rows to
+// spread over the CUs as the limit lets it have.  totals[kTotPanelMax]
+// receives the most products of any panel (above cap the multiply is aborted:
+// later kernels do nothing) and totals[kTotPanelUsed] the number of panels
+// that hold a row.
 __global__ __launch_bounds__(256) void k_panel_rows(const int64_t* __restrict__ np_pre, int32_t nbrows, int64_t half,
                                                     int32_t np, int64_t cap, int32_t* __restrict__ panels,
                                                     int64_t* __restrict__ totals) {
   __shared__ int32_t bnd[kMaxPanels + 1];
-  __shared__ unsigned long long most;
-  if (threadIdx.x == 0) most = 0;
+  __shared__ unsigned long long most, row_most;
+  __shared__ int32_t used;
+  if (threadIdx.x == 0) {
+    most = 0;
+    row_most = 0;
+    used = 0;
+  }
+  __syncthreads();
+  unsigned long long r = 0;
+  for (int32_t i = threadIdx.x; i < nbrows; i += blockDim.x) {
+    const unsigned long long d = (unsigned long long)(np_pre[i + 1] - np_pre[i]);
+    r = d > r ? d : r;
+  }
+  atomicMax(&row_most, r);
+  __syncthreads();
+  const int64_t R = (int64_t)row_most;
+  const int64_t w = cap - R > half ? cap - R : half;
   for (int32_t p = threadIdx.x; p <= np; p += blockDim.x) {
     int32_t lo = 0, hi = nbrows;
     if (p == np) {
       lo = nbrows;
     } else {
-      const int64_t t = (int64_t)p * half;
+      const int64_t t = (int64_t)p * w;
       while (lo < hi) {
         const int32_t mid = lo + ((hi - lo) >> 1);
         if (np_pre[mid] < t) lo = mid + 1;
@@ -329,11 +328,14 @@ __global__ __launch_bounds__(256) void k_panel_rows(const int64_t* __restrict__ 
     panels[p] = lo;
   }
   __syncthreads();
-  for (int32_t p = threadIdx.x; p < np; p += blockDim.x)
+  for (int32_t p = threadIdx.x; p < np; p += blockDim.x) {
     atomicMax(&most, (unsigned long long)(np_pre[bnd[p + 1]] - np_pre[bnd[p]]));
+    if (bnd[p] < bnd[p + 1]) atomicAdd(&used, 1);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     totals[kTotPanelMax] = (int64_t)most;
+    totals[kTotPanelUsed] = used;
     if ((int64_t)most > cap) totals[kTotAbort] = 1;
   }
 }

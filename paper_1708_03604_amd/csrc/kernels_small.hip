@@ -23,6 +23,7 @@
 // never zeroed: they only reach padded outputs, which are never stored.
 #include <type_traits>
 
+#include "block_scan.h"
 #include "bsmm_internal.h"
 
 namespace bsmm {
@@ -84,28 +85,6 @@ __device__ __forceinline__ int shape_class(const int32_t* __restrict__ c_col_idx
   return (m > 8 ? 2 : 0) + (n > 8 ? 1 : 0);
 }
 
-// Exclusive scan of a packed counter (four 16-bit fields) over 256 threads.
-__device__ uint64_t class_scan(uint64_t v, uint64_t* total) {
-  __shared__ uint64_t wsum[kClassThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[wave] = x;
-  __syncthreads();
-  uint64_t off = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kClassThreads / 64; ++w) {
-    if (w < wave) off += wsum[w];
-    tot += wsum[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + x - v;
-}
 
 // cnt[cls * nchunks + chunk] = number of C blocks of class cls in the chunk.
 __global__ __launch_bounds__(kClassThreads) void k_class_count(const int64_t* __restrict__ totals, int32_t nchunks,
@@ -125,7 +104,7 @@ __global__ __launch_bounds__(kClassThreads) void k_class_count(const int64_t* __
     }
   }
   uint64_t total;
-  (void)class_scan(packed, &total);
+  (void)block_exclusive_scan<kClassThreads>(packed, &total);
   if (threadIdx.x < 4) cnt[(int64_t)threadIdx.x * nchunks + chunk] = (int64_t)((total >> (16 * threadIdx.x)) & 0xffff);
 }
 
@@ -154,7 +133,7 @@ __global__ __launch_bounds__(kClassThreads) void k_class_scatter(
     }
   }
   uint64_t total;
-  uint64_t run = class_scan(packed, &total);
+  uint64_t run = block_exclusive_scan<kClassThreads>(packed, &total);
 #pragma unroll
   for (int u = 0; u < kClassPer; ++u) {
     if (cls[u] >= 0) {

@@ -13,6 +13,7 @@
 //
 // Two passes share the enumeration: the count pass sizes the outputs, the fill
 // pass writes them.  Both take exactly the same keep/drop decisions.
+#include "block_scan.h"
 #include "bsmm_internal.h"
 
 namespace bsmm {
@@ -74,28 +75,6 @@ __device__ __forceinline__ int hash_find(const int32_t* hkey, int32_t j) {
   return -1;
 }
 
-// Exclusive scan over the workgroup (256 threads); *total receives the sum.
-__device__ int64_t sym_scan(int64_t v, int64_t* total) {
-  __shared__ int64_t wsum[kSymThreads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int64_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[wave] = x;
-  __syncthreads();
-  int64_t off = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kSymThreads / 64; ++w) {
-    if (w < wave) off += wsum[w];
-    tot += wsum[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + x - v;
-}
 
 // Row state in LDS common to both passes.
 template <int RA>
@@ -134,7 +113,7 @@ __device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* 
     mysum += len[u];
   }
   int64_t total;
-  int64_t run = sym_scan(mysum, &total);
+  int64_t run = block_exclusive_scan<kSymThreads>(mysum, &total);
   if (total > 0x7fffffffLL) return -1;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -608,7 +587,7 @@ __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, i
     mysum += len[u];
   }
   int64_t total;
-  int64_t run = sym_scan(mysum, &total);
+  int64_t run = block_exclusive_scan<kSymThreads>(mysum, &total);
   if (total > 0x7fffffffLL) return -1;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -782,8 +761,8 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
         sv += vs[u];
       }
       int64_t tc, tv;
-      int64_t rc = sym_scan(sc, &tc);
-      int64_t rv = sym_scan(sv, &tv);
+      int64_t rc = block_exclusive_scan<kSymThreads>(sc, &tc);
+      int64_t rv = block_exclusive_scan<kSymThreads>(sv, &tv);
       const int64_t prow = g.row_pstart[i];
       const int64_t vrow = g.row_vstart[i];
       const int64_t m = g.c_row_sizes[i];
@@ -973,7 +952,13 @@ hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sym_fill_huge, dim3(a.A.nbrows < 512 ? a.A.nbrows : 512), dim3(kSymThreads), 0, s, a);
+  // With stack panels, one workgroup per listed row: a panel's rows lie
+  // anywhere in the list (a strided walk would give some workgroups two of
+  // them and others none), and a workgroup whose row is outside the panel
+  // ends at once (a panelled multiply runs for seconds, so the empty
+  // workgroups cost nothing that shows).
+  const int huge_grid = a.panel ? grid : (a.A.nbrows < 512 ? a.A.nbrows : 512);
+  hipLaunchKernelGGL(k_sym_fill_huge, dim3(huge_grid), dim3(kSymThreads), 0, s, a);
   return hipGetLastError();
 }
 
