@@ -114,7 +114,8 @@ struct bsmm_matrix {
   Storage cur, spare;
   // product stack of the last multiply that wrote this matrix
   DBuf<int64_t> prod_ptr;
-  DBuf<int32_t> prod_a, prod_b, old_idx;
+  DBuf<int2> prod;  // {A block, B block} of every product, in stack order
+  DBuf<int32_t> old_idx;
   int64_t nprod = 0;
   bool has_stack = false;
   bsmm_mult_stats stats{};
@@ -444,8 +445,7 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->d_row_sizes.release();
   m->d_col_sizes.release();
   m->prod_ptr.release();
-  m->prod_a.release();
-  m->prod_b.release();
+  m->prod.release();
   m->old_idx.release();
   m->norm_a.release();
   m->norm_b.release();
@@ -536,12 +536,16 @@ bsmm_status bsmm_export_stack(bsmm_mat C, int32_t* st_c, int32_t* st_a, int32_t*
   const int64_t np = C->nprod;
   std::vector<int64_t> pp(C->nnzb + 1);
   std::vector<int32_t> a(np), b(np), c(np);
+  std::vector<int2> ab(np);
   HIP_TRY(hipMemcpyAsync(pp.data(), C->prod_ptr.p, sizeof(int64_t) * (C->nnzb + 1), hipMemcpyDeviceToHost, s));
   if (np) {
-    HIP_TRY(hipMemcpyAsync(a.data(), C->prod_a.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(b.data(), C->prod_b.p, sizeof(int32_t) * np, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ab.data(), C->prod.p, sizeof(int2) * np, hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
+  for (int64_t y = 0; y < np; ++y) {
+    a[y] = ab[y].x;
+    b[y] = ab[y].y;
+  }
   for (int32_t x = 0; x < C->nnzb; ++x)
     for (int64_t y = pp[x]; y < pp[x + 1]; ++y) c[y] = x;
   const hipMemcpyKind k = ptr_kind == BSMM_PTR_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
@@ -780,8 +784,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   Storage& out = in_place ? C->spare : C->cur;
   if (ensure_storage(out, nbrows, nnzc_bound, nvals_bound) != hipSuccess ||
       C->prod_ptr.ensure(nnzc_bound + 1) != hipSuccess ||
-      C->prod_a.ensure(std::max<int64_t>(stack_bound, 1)) != hipSuccess ||
-      C->prod_b.ensure(std::max<int64_t>(stack_bound, 1)) != hipSuccess ||
+      C->prod.ensure(std::max<int64_t>(stack_bound, 1)) != hipSuccess ||
       C->old_idx.ensure(std::max<int64_t>(nnzc_bound, 1)) != hipSuccess)
     return empty_result(C, s, BSMM_E_NOMEM, "device allocation for the result failed");
   const bool small = !split && !slice && uniform != 23 && std::max(A->max_edge, B->max_edge) <= kSmallEdge;
@@ -822,8 +825,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.c_blk_off = out.blk_off.p;
   g.prod_ptr = C->prod_ptr.p;
   g.c_old_idx = C->old_idx.p;
-  g.prod_a = C->prod_a.p;
-  g.prod_b = C->prod_b.p;
+  g.prod = C->prod.p;
 
   NumArgs na{};
   na.A = g.A;
@@ -840,8 +842,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.c_blk_off = out.blk_off.p;
   na.prod_ptr = C->prod_ptr.p;
   na.c_old_idx = C->old_idx.p;
-  na.prod_a = C->prod_a.p;
-  na.prod_b = C->prod_b.p;
+  na.prod = C->prod.p;
   na.c_values = out.values.p;
   na.wide_inner = (A->col_edges & 0x7fffu) == 0;  // no inner block edge below 16
   na.uniform = uniform;
@@ -1079,7 +1080,7 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
   // A's row and B's column edges, so an edge above kSmallEdge rules it out
   const bool small_ok = m->max_edge <= kSmallEdge;
   bool ok = ensure_storage(m->spare, nbrows, cb, cv) == hipSuccess && m->prod_ptr.ensure(cb + 1) == hipSuccess &&
-            m->prod_a.ensure(cstack) == hipSuccess && m->prod_b.ensure(cstack) == hipSuccess &&
+            m->prod.ensure(cstack) == hipSuccess &&
             m->panels.ensure(npanels + 1) == hipSuccess &&
             m->old_idx.ensure(cb) == hipSuccess &&
             (!small_ok ||

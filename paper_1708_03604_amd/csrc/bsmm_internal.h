@@ -99,8 +99,7 @@ struct SymArgs {
   int64_t* c_blk_off;
   int64_t* prod_ptr;    // [nnzc+1] start of each C block's products
   int32_t* c_old_idx;   // [nnzc] block of C_in or -1
-  int32_t* prod_a;      // [nprod]
-  int32_t* prod_b;      // [nprod]
+  int2* prod;           // [nprod] {A block, B block} of every product
   const int64_t* totals;  // per-multiply totals (the fill does nothing once aborted)
 };
 
@@ -116,13 +115,12 @@ struct NumArgs {
   const int64_t* c_blk_off;
   const int64_t* prod_ptr;
   const int32_t* c_old_idx;
-  const int32_t* prod_a;
-  const int32_t* prod_b;
+  const int2* prod;
   double* c_values;
   int wide_inner;          // every inner block edge >= 16: the generic path may use the matrix-core form
   int uniform;             // common edge of every block of A and B, or 0
   // 23x23 paths: only the C blocks of rows [panel[0], panel[1]) are computed,
-  // and prod_a/prod_b hold that panel's products from index 0; nullptr = all
+  // and prod holds that panel's products from index 0; nullptr = all
   const int32_t* panel;
   const int32_t* c_row_ptr;
 };
@@ -183,7 +181,7 @@ int64_t numeric_work_elems();
 constexpr int kSliceParts = 8;  // one per XCD
 int32_t launch_product_slices(const int64_t* prod_ptr, const int64_t* totals, const int32_t* c_row_ptr,
                               const int32_t* panel, int32_t* work, hipStream_t s);
-// Stack position that index 0 of prod_a/prod_b holds, stored after the
+// Stack position that index 0 of prod holds, stored after the
 // slice bounds by k_product_slices.
 __device__ __forceinline__ int64_t slices_pbase(const int32_t* bounds, int32_t ns) {
   return *reinterpret_cast<const int64_t*>(bounds + kSliceParts * (ns + 1));

@@ -52,10 +52,11 @@ struct MidCursor {
 
 __device__ __forceinline__ void mid_product(const NumArgs& g, MidCursor& u) {
   if (u.x < u.x1) {
-    const int32_t a = g.prod_a[u.x];
+    const int2 ab = g.prod[u.x];
+    const int32_t a = ab.x;
     const int64_t a0 = g.A.blk_off[a], a1 = g.A.blk_off[a + 1];
     u.aoff = a0;
-    u.boff = g.B.blk_off[g.prod_b[u.x]];
+    u.boff = g.B.blk_off[ab.y];
     u.k = (int32_t)((uint32_t)(a1 - a0) / (uint32_t)u.m);
   } else {
     u.k = 0;  // C block without products: one empty chunk finishes each sub-tile
@@ -318,7 +319,7 @@ constexpr int kMfmaOperand = kTileEdge * kMfmaStride;
 template <int S>
 __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
     const double* __restrict__ Av, const double* __restrict__ Bv, const double* __restrict__ Ov,
-    const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
+    const int64_t* __restrict__ prod_ptr, const int2* __restrict__ prod,
     const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals, int use_old,
     double alpha, double beta, const int32_t* __restrict__ bounds, int32_t ns) {
   static_assert(S >= 17 && S <= kTileEdge, "matrix-core kernel covers edges 17..24");
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   const int32_t nnzc = live_nnzc(totals);
   if (nnzc == 0) return;
   const int32_t* const bnd = bounds + xcd * (ns + 1);
-  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod_a[0]
+  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod[0]
 
   // fetch cursor: slice iq, products [ip, ip_end)
   int32_t iq = wix;
@@ -375,13 +376,15 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
   {
     const int64_t n0 = next_index();
     if (n0 >= 0) {
-      qa0 = prod_a[n0 - pbase];
-      qb0 = prod_b[n0 - pbase];
+      const int2 e0 = prod[n0 - pbase];
+      qa0 = e0.x;
+      qb0 = e0.y;
     }
     const int64_t n1 = next_index();
     if (n1 >= 0) {
-      qa1 = prod_a[n1 - pbase];
-      qb1 = prod_b[n1 - pbase];
+      const int2 e1 = prod[n1 - pbase];
+      qa1 = e1.x;
+      qb1 = e1.y;
     }
   }
   double opa[PER], opb[PER];
@@ -400,8 +403,9 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mfma24(
     qa0 = qa1;
     qb0 = qb1;
     const int64_t n = next_index();
-    qa1 = n >= 0 ? prod_a[n - pbase] : -1;
-    qb1 = n >= 0 ? prod_b[n - pbase] : -1;
+    const int2 e = n >= 0 ? prod[n - pbase] : make_int2(-1, -1);
+    qa1 = e.x;
+    qb1 = e.y;
   };
   auto stage_write = [&](const int st) {
     double* base = &lds[wv][st][0];
@@ -575,7 +579,7 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
     const int32_t blocks = tile23_grid();
     const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, a.c_row_ptr, a.panel, work, s);
     hipLaunchKernelGGL(k_numeric_mfma24<23>, dim3(blocks), dim3(256), 0, s, a.A.values, a.B.values,
-                       a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
+                       a.use_old ? a.Cin.values : a.A.values, a.prod_ptr, a.prod, a.c_old_idx,
                        a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);
     return hipGetLastError();
   }

@@ -176,8 +176,7 @@ __global__ __launch_bounds__(kClassThreads) void k_class_scatter(
 __global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ totals,
                                                     const int4* __restrict__ list,
                                                     const int64_t* __restrict__ qstart,
-                                                    const int32_t* __restrict__ prod_a,
-                                                    const int32_t* __restrict__ prod_b,
+                                                    const int2* __restrict__ prod,
                                                     const int64_t* __restrict__ Aoff,
                                                     const int64_t* __restrict__ Boff, int32_t ue,
                                                     int4* __restrict__ desc) {
@@ -196,7 +195,8 @@ __global__ __launch_bounds__(256) void k_class_desc(const int64_t* __restrict__ 
     const int64_t q = qstart[e];
     for (int32_t l = l0; l < ent.z; l += 16) {
       const int64_t p = (int64_t)ent.y + l;
-      const int32_t a = prod_a[p], b = prod_b[p];
+      const int2 ab = prod[p];
+      const int32_t a = ab.x, b = ab.y;
       int64_t ao, bo;
       int32_t k;
       if (ue) {
@@ -1223,8 +1223,7 @@ hipError_t launch_class_lists(const NumArgs& a, int64_t* cnt, int64_t* cnt_pre, 
   if (e != hipSuccess) return e;
   int64_t blocks = (a.nnzc_bound + 15) / 16;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_class_desc, dim3((uint32_t)blocks), dim3(256), 0, s, a.totals, list, qstart, a.prod_a,
-                     a.prod_b, a.A.blk_off, a.B.blk_off, (int32_t)a.uniform, desc);
+  hipLaunchKernelGGL(k_class_desc, dim3((uint32_t)blocks), dim3(256), 0, s, a.totals, list, qstart, a.prod, a.A.blk_off, a.B.blk_off, (int32_t)a.uniform, desc);
   return hipGetLastError();
 }
 

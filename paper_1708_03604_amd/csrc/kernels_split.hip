@@ -106,7 +106,7 @@ __device__ __forceinline__ void wsync() {
 // stage per wave, written after the previous product has been read.
 __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     const uint16_t* __restrict__ As, const uint16_t* __restrict__ Bs, const double* __restrict__ Ov,
-    const int64_t* __restrict__ prod_ptr, const int32_t* __restrict__ prod_a, const int32_t* __restrict__ prod_b,
+    const int64_t* __restrict__ prod_ptr, const int2* __restrict__ prod,
     const int32_t* __restrict__ c_old_idx, double* __restrict__ Cv, const int64_t* __restrict__ totals,
     int use_old, double alpha, double beta, const int32_t* __restrict__ bounds, int32_t ns) {
   constexpr int NE = kE * kE;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
   const int32_t wpx = (int32_t)(gridDim.x / kXcds) * 4;
   const int32_t wix = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / kXcds) * 4 + wv);
   const int32_t* const bnd = bounds + xcd * (ns + 1);
-  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod_a[0]
+  const int64_t pbase = slices_pbase(bounds, ns);  // stack position of prod[0]
 
   // fetch cursor: slice iq of the XCD's part, products [ip, ip_end)
   int32_t iq = wix;
@@ -158,13 +158,15 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
   {
     const int64_t n0 = next_index();
     if (n0 >= 0) {
-      qa0 = prod_a[n0 - pbase];
-      qb0 = prod_b[n0 - pbase];
+      const int2 e0 = prod[n0 - pbase];
+      qa0 = e0.x;
+      qb0 = e0.y;
     }
     const int64_t n1 = next_index();
     if (n1 >= 0) {
-      qa1 = prod_a[n1 - pbase];
-      qb1 = prod_b[n1 - pbase];
+      const int2 e1 = prod[n1 - pbase];
+      qa1 = e1.x;
+      qb1 = e1.y;
     }
   }
   // two register slots, as separately named arrays (kept in registers)
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(256, 2) void k_numeric_split23(
     qa0 = qa1;
     qb0 = qb1;
     const int64_t n = next_index();
-    qa1 = n >= 0 ? prod_a[n - pbase] : -1;
-    qb1 = n >= 0 ? prod_b[n - pbase] : -1;
+    const int2 e = n >= 0 ? prod[n - pbase] : make_int2(-1, -1);
+    qa1 = e.x;
+    qb1 = e.y;
   };
   auto stage_write = [&](const u32x4(&opa)[kPer], const u32x4(&opb)[kPer]) __attribute__((always_inline)) {
 #pragma unroll
@@ -346,7 +349,7 @@ hipError_t launch_numeric_split23(const NumArgs& a, const uint16_t* As, const ui
   if (a.nnzc_bound <= 0) return hipSuccess;
   const int32_t ns = launch_product_slices(a.prod_ptr, a.totals, a.c_row_ptr, a.panel, work, s);
   hipLaunchKernelGGL(k_numeric_split23, dim3(tile23_workgroups()), dim3(256), 0, s, As, Bs,
-                     a.use_old ? a.Cin.values : a.c_values, a.prod_ptr, a.prod_a, a.prod_b, a.c_old_idx,
+                     a.use_old ? a.Cin.values : a.c_values, a.prod_ptr, a.prod, a.c_old_idx,
                      a.c_values, a.totals, a.use_old, a.alpha, a.beta, work, ns);
   return hipGetLastError();
 }

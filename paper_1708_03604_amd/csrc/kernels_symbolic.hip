@@ -472,8 +472,7 @@ __global__ __launch_bounds__(256) void k_sym_fill_thin(SymArgs g) {
 #pragma unroll
       for (int y = 0; y < kThinT; ++y) {
         if (y < r.n && r.cj[y] == j) {
-          g.prod_a[srow + pc] = r.a0 + r.cp[y];
-          g.prod_b[srow + pc] = r.cq[y];
+          g.prod[srow + pc] = make_int2(r.a0 + r.cp[y], r.cq[y]);
           ++pc;
         }
       }
@@ -838,8 +837,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
             const int32_t p = rh;
             const uint32_t below = rmask[r] & ((1u << (p - r0)) - 1u);
             const int32_t pos = spre[r] + cursor[r] + __builtin_popcount(below);
-            g.prod_a[prow + pos] = a0 + p;
-            g.prod_b[prow + pos] = ra.qs[p] + (t - ra.pre[p]);
+            g.prod[prow + pos] = make_int2(a0 + p, ra.qs[p] + (t - ra.pre[p]));
           }
         }
         __syncthreads();
