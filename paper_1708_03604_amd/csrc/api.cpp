@@ -270,6 +270,9 @@ bsmm_status sync_sizes(bsmm_matrix* m, hipStream_t s) {
   m->stats.nnzb = t[kTotNnzc];
   m->stats.nvals = t[kTotNvals];
   m->stats.useful_flops = 2.0 * (double)t[kTotFlopHalf];
+  // a reserved multiply in stack panels launches every panel its capacity
+  // allows; the device counted the ones that held a row
+  if (m->stats.panels > 1 && t[kTotPanelUsed] > 0) m->stats.panels = (int32_t)t[kTotPanelUsed];
   return BSMM_OK;
 }
 
