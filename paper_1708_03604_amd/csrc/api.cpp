@@ -87,7 +87,7 @@ struct Storage {
 };
 
 constexpr int64_t kValueSlack = kValueSlackDoubles;
-constexpr int kPinned = 16;
+constexpr int kPinned = 32;
 // Default stack limit: 2^30 products (8 GB of stack indices); a 23x23
 // multiply with more products builds and consumes its stack in panels.
 constexpr int64_t kDefaultStackLimit = int64_t(1) << 30;
@@ -650,7 +650,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   // allocates or synchronises (graph-capturable); the bounds are capacities.
   const bool reserved = C->cap_nnzb > 0;
   // scratch
-  if (C->flags.ensure(3) != hipSuccess || C->work.ensure(numeric_work_elems()) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
+  if (C->flags.ensure(4) != hipSuccess || C->work.ensure(numeric_work_elems()) != hipSuccess || C->totals.ensure(kTotCount) != hipSuccess ||
       C->scan_tmp.ensure(scan_tmp_elems(nbrows) + 2) != hipSuccess)
     return fail(BSMM_E_NOMEM, "scratch allocation failed");
   for (int x = 0; x < 5; ++x)
@@ -675,7 +675,8 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       normB = C->norm_b.p;
     }
   }
-  HIP_TRY(launch_zero_u32(C->flags.p, 3, s));  // symbolic-pass flags, the wide- and huge-row counts
+  // symbolic-pass flags, the wide- and huge-row counts, the fill forms needed
+  HIP_TRY(launch_zero_u32(C->flags.p, 4, s));
   mark(C, ev, 1, s);
 
   SymArgs g{};
@@ -700,6 +701,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.n_wide = reinterpret_cast<int32_t*>(C->flags.p + 1);
   g.huge = C->huge.p;
   g.n_huge = reinterpret_cast<int32_t*>(C->flags.p + 2);
+  g.forms = C->flags.p + 3;
   g.totals = C->totals.p;
   HIP_TRY(launch_sym_count(g, s));
   {
@@ -720,6 +722,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   const bool panel_ok = uniform == 23;
   int32_t npanels = 1;
   int32_t used_panels = 0;  // eager multiplies: the panels that hold a row (the rest are empty)
+  uint32_t fill_mask = kFillAll;  // eager multiplies: only the fill forms the count pass found rows for
   int64_t nnzc = 0, nprod = 0, nvals = 0, ncand = 0, nflop_half = 0;
   int64_t nnzc_bound, nprod_bound, nvals_bound, stack_bound;
   if (reserved) {
@@ -741,6 +744,14 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     nvals = C->h_totals[kTotNvals];
     ncand = C->h_totals[kTotCand];
     nflop_half = C->h_totals[kTotFlopHalf];
+    {
+      // launch only the fill forms some row needs
+      const int64_t nw = C->h_totals[kTotWide], nh = C->h_totals[kTotHuge];
+      const uint32_t forms = (uint32_t)C->h_totals[kTotForms];
+      fill_mask = (nw < nbrows ? kFillThin : 0u) | (nw > nh ? kFillTiny : 0u) |
+                  ((forms & kFormSmall) ? kFillSmall : 0u) | ((forms & kFormLarge) ? kFillLarge : 0u) |
+                  (nh > 0 ? kFillHuge : 0u);
+    }
     const uint32_t flags = (uint32_t)C->h_totals[kTotFlags];
     if (flags & kFlagRowTooManyA)
       return fail(BSMM_E_UNSUPPORTED, "an A block row holds more than " + std::to_string(kMaxRowA) + " blocks");
@@ -857,7 +868,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   for (int32_t pnl = 0; pnl < npanels; ++pnl) {
     g.panel = npanels > 1 ? C->panels.p + pnl : nullptr;
     na.panel = g.panel;
-    HIP_W(launch_sym_fill(g, s));
+    HIP_W(launch_sym_fill(g, fill_mask, s));
     if (pnl == 0) mark(C, ev, 4, s);
     if (split) {
       if (pnl == 0) {
@@ -1092,7 +1103,7 @@ bsmm_status bsmm_reserve(bsmm_mat m, int64_t max_nnzb, int64_t max_nvals, int64_
               m->class_start.ensure(5) == hipSuccess && m->class_np.ensure(nce) == hipSuccess &&
               m->class_q.ensure(nce + 1) == hipSuccess)) &&
             m->scan_tmp.ensure(tmp) == hipSuccess && m->totals.ensure(kTotCount) == hipSuccess &&
-            m->flags.ensure(3) == hipSuccess && m->work.ensure(numeric_work_elems()) == hipSuccess &&
+            m->flags.ensure(4) == hipSuccess && m->work.ensure(numeric_work_elems()) == hipSuccess &&
             m->norm_a.ensure(cb) == hipSuccess && m->norm_b.ensure(cb) == hipSuccess &&
             m->norm_self.ensure(cb) == hipSuccess && m->fkeep.ensure(cb + 1) == hipSuccess &&
             m->fvsz.ensure(cb + 1) == hipSuccess && m->fpos.ensure(cb + 1) == hipSuccess &&

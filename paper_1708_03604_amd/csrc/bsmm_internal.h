@@ -50,7 +50,26 @@ enum : int {
   kTotAbort = 6,     // nonzero: the result does not fit; later kernels do nothing
   kTotPanelMax = 7,  // most products of any stack panel (panelled multiplies)
   kTotPanelUsed = 8, // stack panels that hold a block row (panelled multiplies)
-  kTotCount = 9
+  kTotWide = 9,      // block rows the count pass left to the workgroup forms
+  kTotHuge = 10,     // block rows left to the huge forms
+  kTotForms = 11,    // kForm* bits: fill forms beyond the tiny one that some row needs
+  kTotCount = 12
+};
+
+// Row limits of the two smallest workgroup forms of the fill pass (stored A
+// blocks, result blocks); rows beyond the small form's take the large form.
+constexpr int kTinyRowA = 128, kTinyRowC = 256;
+constexpr int kSmallRowA = 256, kSmallRowC = 512;
+enum : uint32_t {
+  kFormSmall = 1u,  // some row exceeds the tiny form and fits the small one
+  kFormLarge = 2u,  // some row exceeds the small form (and is no huge row)
+};
+// Fill launches (launch_sym_fill): an eager multiply launches only the forms
+// the count pass found rows for (and the thin form whenever the stack is built
+// in panels: it writes each panel's end offset); a reserved one (graph)
+// launches all.
+enum : uint32_t {
+  kFillThin = 1u, kFillTiny = 2u, kFillSmall = 4u, kFillLarge = 8u, kFillHuge = 16u, kFillAll = 31u,
 };
 
 // Doubles of zero slack kept after the last value of every matrix: the
@@ -87,6 +106,7 @@ struct SymArgs {
   // rows the ordinary forms leave to the huge forms (listed the same way)
   int32_t* huge;       // [nbrows]
   int32_t* n_huge;
+  uint32_t* forms;     // kForm* bits raised by the count pass (zero when it starts)
   // fill pass: only rows [panel[0], panel[1]) are filled, and their products
   // are written from stack position row_pstart[panel[0]] on at index 0 (the
   // stack holds one panel of rows); nullptr = every row, one stack
@@ -164,7 +184,7 @@ hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, in
                      hipStream_t s);
 
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s);
-hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s);
+hipError_t launch_sym_fill(const SymArgs& a, uint32_t launch_mask, hipStream_t s);
 hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,
                               int32_t* c_row_ptr, int64_t* prod_ptr, int64_t* c_blk_off, const int64_t* totals,
                               hipStream_t s);

@@ -245,15 +245,30 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
 // ---------------------------------------------------------------------------
 constexpr int kTileEdge = 24;
 
-// First c in [lo, hi] with prod_ptr[c] >= t (prod_ptr is non-decreasing),
-// hi if there is none.
-__device__ __forceinline__ int32_t lower_bound_c(const int64_t* prod_ptr, int32_t lo, int32_t hi, int64_t t) {
-  while (lo < hi) {
-    const int32_t mid = lo + ((hi - lo) >> 1);
-    if (prod_ptr[mid] < t) lo = mid + 1;
-    else hi = mid;
+// For each of three targets t, the first c in [lo, hi] with prod_ptr[c] >= t
+// (prod_ptr is non-decreasing), hi if there is none: a branchless search
+// whose step count depends only on hi - lo, so the three loads of each step
+// are in flight together (the schedule pass is bound by these dependent
+// loads, not by arithmetic).
+__device__ __forceinline__ void lower_bound_c3(const int64_t* __restrict__ prod_ptr, int32_t lo, int32_t hi,
+                                               const int64_t (&t)[3], int32_t (&r)[3]) {
+  int32_t b[3] = {lo, lo, lo};
+  if (hi > lo) {
+    int32_t n = hi - lo;
+    while (n > 1) {  // invariant: the answer lies in [b, b + n]
+      const int32_t half = n >> 1;
+      int64_t v[3];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) v[s] = prod_ptr[b[s] + half];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) b[s] = v[s] < t[s] ? b[s] + half : b[s];
+      n -= half;
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) b[s] += prod_ptr[b[s]] < t[s] ? 1 : 0;
   }
-  return lo;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) r[s] = b[s];
 }
 
 // Schedule of the 23x23 kernels: the C blocks [c0, c1) of the panel (all
@@ -282,12 +297,15 @@ __global__ void k_product_slices(const int64_t* __restrict__ prod_ptr, const int
   for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < kKernelXcds * per; t += gridDim.x * 256) {
     const int32_t x = t / per, j = t - x * per;
     const int64_t p0 = pb + P * x / kKernelXcds, p1 = pb + P * (x + 1) / kKernelXcds;
-    const int32_t X0 = x == 0 ? c0 : lower_bound_c(prod_ptr, c0, c1, p0);
-    const int32_t X1 = x == kKernelXcds - 1 ? c1 : lower_bound_c(prod_ptr, c0, c1, p1);
+    const int64_t tg[3] = {p0, p1, p0 + (p1 - p0) * j / ns};
+    int32_t r[3];
+    lower_bound_c3(prod_ptr, c0, c1, tg, r);
+    const int32_t X0 = x == 0 ? c0 : r[0];
+    const int32_t X1 = x == kKernelXcds - 1 ? c1 : r[1];
     int32_t b;
     if (j == 0) b = X0;
     else if (j == ns) b = X1;
-    else b = min(X1, max(X0, lower_bound_c(prod_ptr, c0, c1, p0 + (p1 - p0) * j / ns)));
+    else b = min(X1, max(X0, r[2]));
     bounds[t] = b;
   }
 }

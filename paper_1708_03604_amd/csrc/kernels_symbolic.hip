@@ -294,6 +294,9 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
         g.row_nv[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_sumn;
         g.row_ncand[i] = T;
         g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
+        // the fill forms beyond the tiny one this row needs (few rows do)
+        if (DEFER && !bad && (nA > kTinyRowA || s_nc > kTinyRowC))
+          atomicOr(g.forms, (nA <= kSmallRowA && s_nc <= kSmallRowC) ? kFormSmall : kFormLarge);
       }
     }
     __syncthreads();
@@ -553,8 +556,8 @@ struct FillCaps {
   static_assert((RA % kSymThreads == 0 || RA < kSymThreads) && RB % kSymThreads == 0, "row chunking");
   static_assert(2 * RB <= kSlots, "hash load at most one half");
 };
-using FillTiny = FillCaps<9, 128, 256, 4096>;
-using FillSmall = FillCaps<10, 256, 512, 4096>;
+using FillTiny = FillCaps<9, kTinyRowA, kTinyRowC, 4096>;
+using FillSmall = FillCaps<10, kSmallRowA, kSmallRowC, 4096>;
 struct FillNone {  // no form: no row fits
   static constexpr int kRowA = -1, kRowC = -1;
 };
@@ -935,29 +938,40 @@ hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sym_fill(const SymArgs& a, hipStream_t s) {
+hipError_t launch_sym_fill(const SymArgs& a, uint32_t launch_mask, hipStream_t s) {
   if (a.A.nbrows <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sym_fill_thin, dim3((a.A.nbrows + 255) / 256), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  // the thin form also writes a stack panel's end offset (prod_ptr after the
+  // panel's last C block), which the numeric pass reads: with panels it runs
+  // whether or not any row is thin
+  if ((launch_mask & kFillThin) || a.panel) {
+    hipLaunchKernelGGL(k_sym_fill_thin, dim3((a.A.nbrows + 255) / 256), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int grid = a.A.nbrows < 65536 ? a.A.nbrows : 65536;
-  hipLaunchKernelGGL((k_sym_fill_form<FillTiny, FillNone>), dim3(grid), dim3(kSymThreads), 0, s, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sym_fill_form<FillSmall, FillTiny>), dim3(grid), dim3(kSymThreads), 0, s, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // With stack panels, one workgroup per listed row: a panel's rows lie
-  // anywhere in the list (a strided walk would give some workgroups two of
-  // them and others none), and a workgroup whose row is outside the panel
-  // ends at once (a panelled multiply runs for seconds, so the empty
-  // workgroups cost nothing that shows).
-  const int huge_grid = a.panel ? grid : (a.A.nbrows < 512 ? a.A.nbrows : 512);
-  hipLaunchKernelGGL(k_sym_fill_huge, dim3(huge_grid), dim3(kSymThreads), 0, s, a);
-  return hipGetLastError();
+  if (launch_mask & kFillTiny) {
+    hipLaunchKernelGGL((k_sym_fill_form<FillTiny, FillNone>), dim3(grid), dim3(kSymThreads), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (launch_mask & kFillSmall) {
+    hipLaunchKernelGGL((k_sym_fill_form<FillSmall, FillTiny>), dim3(grid), dim3(kSymThreads), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (launch_mask & kFillLarge) {
+    hipLaunchKernelGGL(k_sym_fill_large, dim3(a.A.nbrows < 8192 ? a.A.nbrows : 8192), dim3(kSymThreads), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (launch_mask & kFillHuge) {
+    // With stack panels, one workgroup per listed row: a panel's rows lie
+    // anywhere in the list (a strided walk would give some workgroups two of
+    // them and others none), and a workgroup whose row is outside the panel
+    // ends at once (a panelled multiply runs for seconds, so the empty
+    // workgroups cost nothing that shows).
+    const int huge_grid = a.panel ? grid : (a.A.nbrows < 512 ? a.A.nbrows : 512);
+    hipLaunchKernelGGL(k_sym_fill_huge, dim3(huge_grid), dim3(kSymThreads), 0, s, a);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // c_row_ptr (int32) from the int64 prefix of per-row block counts; closes the
@@ -998,6 +1012,9 @@ __global__ void k_gather_totals(int32_t n, const int64_t* nc_pre, const int64_t*
     totals[4] = (int64_t)*flags;
     totals[5] = nf_pre[n];
     totals[kTotAbort] = 0;
+    totals[kTotWide] = (int64_t)flags[1];
+    totals[kTotHuge] = (int64_t)flags[2];
+    totals[kTotForms] = (int64_t)flags[3];
   }
 }
 
