@@ -401,6 +401,59 @@ hipError_t launch_frobenius(const double* values, const int64_t* d_nvals, double
   return hipGetLastError();
 }
 
+// The same for n <= kRowScanThreads * kRowScanItems rows in one pass: each
+// thread loads its kRowScanItems consecutive rows of every array first (one
+// round of loads instead of one per 1024 rows), the workgroup scans the
+// per-thread sums, and each thread writes its rows' prefixes.
+constexpr int kRowScanItems = 4;
+__global__ __launch_bounds__(kRowScanThreads) void k_scan_rows_one(ScanSet set, int narr, int64_t n) {
+  __shared__ int64_t wsum[8][kRowScanThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)threadIdx.x * kRowScanItems;
+  int64_t v[8][kRowScanItems], x[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    x[a] = 0;
+#pragma unroll
+    for (int u = 0; u < kRowScanItems; ++u) {
+      v[a][u] = (a < narr && i0 + u < n) ? set.in[a][i0 + u] : 0;
+      x[a] += v[a][u];
+    }
+  }
+  int64_t t[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) t[a] = x[a];
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int64_t y = __shfl_up(x[a], d, 64);
+      if (lane >= d) x[a] += y;
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) wsum[a][wave] = x[a];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    if (a >= narr) continue;
+    int64_t run = x[a] - t[a];
+    for (int w = 0; w < wave; ++w) run += wsum[a][w];
+#pragma unroll
+    for (int u = 0; u < kRowScanItems; ++u) {
+      if (i0 + u < n) set.out[a][i0 + u] = run;
+      run += v[a][u];
+    }
+  }
+  if (threadIdx.x < narr) {
+    int64_t tot = 0;
+    for (int w = 0; w < kRowScanThreads / 64; ++w) tot += wsum[threadIdx.x][w];
+    set.out[threadIdx.x][n] = tot;
+  }
+}
+
 hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, int64_t n, int64_t* tmp,
                      hipStream_t s) {
   if (n > (1 << 16)) {
@@ -415,7 +468,10 @@ hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, in
     set.in[a] = in[a];
     set.out[a] = out[a];
   }
-  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kRowScanThreads), 0, s, set, narr, n);
+  if (n <= (int64_t)kRowScanThreads * kRowScanItems)
+    hipLaunchKernelGGL(k_scan_rows_one, dim3(1), dim3(kRowScanThreads), 0, s, set, narr, n);
+  else
+    hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kRowScanThreads), 0, s, set, narr, n);
   return hipGetLastError();
 }
 
