@@ -91,6 +91,10 @@ constexpr int kPinned = 32;
 // Default stack limit: 2^30 products (8 GB of stack indices); a 23x23
 // multiply with more products builds and consumes its stack in panels.
 constexpr int64_t kDefaultStackLimit = int64_t(1) << 30;
+// B blocks per B block row from which a filtered multiply enumerates kept
+// prefixes (molecule rows of ~26 blocks stay below it; semi-empirical rows of
+// ~84 and the sign chain's rows of hundreds to 2048 blocks are above it).
+constexpr int64_t kSortedRowAvg = 48;
 
 // Panels for `products` block products under a stack limit (half the limit
 // per panel start, plus one: see launch_panel_rows).
@@ -129,6 +133,9 @@ struct bsmm_matrix {
   DBuf<double> frob_tmp;
   // scratch
   DBuf<double> norm_a, norm_b, norm_self;
+  DBuf<int32_t> bord, akeep;   // B rows in norm order, kept prefixes of A entries (filtered multiplies)
+  DBuf<double> bnrm;           // the norms in that order
+  DBuf<uint8_t> bsorted;       // B rows that have an order
   DBuf<int64_t> rows[5], pre[5], scan_tmp, totals, fkeep, fvsz, fpos, fvoff;
   DBuf<uint32_t> flags;
   DBuf<int32_t> work;
@@ -452,6 +459,10 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->old_idx.release();
   m->norm_a.release();
   m->norm_b.release();
+  m->bord.release();
+  m->akeep.release();
+  m->bnrm.release();
+  m->bsorted.release();
   m->norm_self.release();
   for (auto& b : m->rows) b.release();
   for (auto& b : m->pre) b.release();
@@ -675,6 +686,20 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       normB = C->norm_b.p;
     }
   }
+  // Filtered multiplies over long B rows enumerate only the kept products of
+  // each A entry (a prefix of its B row in descending norm order); short rows
+  // gain less from it than the sort costs.  Results are the same either way.
+  const int64_t b_blocks = B->cap_nnzb > 0 ? B->cap_nnzb : B->nnzb;
+  const bool sorted_mode = use_eps && b_blocks >= kSortedRowAvg * (int64_t)B->nbrows;
+  if (sorted_mode) {
+    const int64_t ba = blocks_bound(A), bb = blocks_bound(B);
+    if (C->bord.ensure(std::max<int64_t>(bb, 1)) != hipSuccess ||
+        C->bnrm.ensure(std::max<int64_t>(bb, 1)) != hipSuccess ||
+        C->bsorted.ensure(std::max<int64_t>(B->nbrows, 1)) != hipSuccess ||
+        C->akeep.ensure(std::max<int64_t>(ba, 1)) != hipSuccess)
+      return fail(BSMM_E_NOMEM, "scratch allocation failed");
+    HIP_TRY(launch_sort_row_norms(view(B), normB, C->bord.p, C->bnrm.p, C->bsorted.p, s));
+  }
   // symbolic-pass flags, the wide- and huge-row counts, the fill forms needed
   HIP_TRY(launch_zero_u32(C->flags.p, 4, s));
   mark(C, ev, 1, s);
@@ -688,6 +713,11 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   g.eps = filter_eps;
   g.normA = normA;
   g.normB = normB;
+  g.sorted_mode = sorted_mode ? 1 : 0;
+  g.bord = C->bord.p;
+  g.bnrm = C->bnrm.p;
+  g.bsorted = C->bsorted.p;
+  g.akeep = C->akeep.p;
   g.c_row_sizes = C->d_row_sizes.p;
   g.c_col_sizes = C->d_col_sizes.p;
   g.c_col_uniform = C->col_uniform;

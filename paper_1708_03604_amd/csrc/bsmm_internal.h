@@ -89,6 +89,18 @@ struct SymArgs {
   double eps;
   const double* normA;  // [A.nnzb] (only if use_eps)
   const double* normB;  // [B.nnzb] (only if use_eps)
+  // Kept prefixes (only if sorted_mode, which needs use_eps): each B block row
+  // in descending norm order, bord[row_ptr[k] + r] the B block of rank r and
+  // bnrm its norm (rows of more than kSortRow blocks stay unsorted,
+  // bsorted[k] = 0).  The products an A entry keeps on a sorted B row are
+  // then the first akeep[A entry] of that order (the norm product is
+  // monotone in the B norm, so the filter's test selects a prefix): the row
+  // passes enumerate only those, the count pass writing akeep for the fill.
+  int sorted_mode;
+  const int32_t* bord;    // [B.nnzb]
+  const double* bnrm;     // [B.nnzb]
+  const uint8_t* bsorted; // [B.nbrows]
+  int32_t* akeep;         // [A.nnzb]
   const int32_t* c_row_sizes;
   const int32_t* c_col_sizes;
   int32_t c_col_uniform;  // common size of every block column of C, or 0 (then c_col_sizes is read)
@@ -183,6 +195,12 @@ hipError_t scan_exclusive(const int64_t* in, int64_t n, int64_t* out, int64_t* t
 hipError_t scan_rows(const int64_t* const* in, int64_t* const* out, int narr, int64_t n, int64_t* tmp,
                      hipStream_t s);
 
+// Rank the entries of every B block row by descending norm (ties by block
+// index): bord/bnrm/bsorted as described in SymArgs.  B rows of more than
+// kSortRow blocks are left unsorted.
+constexpr int kSortRow = 2048;
+hipError_t launch_sort_row_norms(const MatView& B, const double* normB, int32_t* bord, double* bnrm,
+                                 uint8_t* bsorted, hipStream_t s);
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s);
 hipError_t launch_sym_fill(const SymArgs& a, uint32_t launch_mask, hipStream_t s);
 hipError_t launch_finish_rows(int32_t nbrows, const int64_t* nc_pre, const int64_t* np_pre, const int64_t* nv_pre,

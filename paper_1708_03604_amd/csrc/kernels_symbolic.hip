@@ -81,14 +81,30 @@ template <int RA>
 struct RowA {
   int32_t qs[RA];        // first B block of B row k_p
   int32_t ks[RA];        // inner block size of k_p
-  int32_t pre[RA + 1];   // exclusive prefix of B row lengths
+  int32_t pre[RA + 1];   // exclusive prefix of the enumerated candidates per entry
   double nrm[RA];        // norm of A(i, k_p)
+  int8_t srt[RA];        // B row k_p enumerated in norm order (its kept prefix only)
 };
 
+// Kept prefix of A entry e (norm a) on B row k (sorted, n blocks from q0):
+// the number of its entries whose product with a passes the filter.
+__device__ __forceinline__ int32_t kept_prefix(const SymArgs& g, double a, int32_t q0, int32_t n) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a * g.bnrm[q0 + mid] > g.eps) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Load the A entries of row i and the candidate prefix.  Returns the number of
-// candidates T (or -1 if the row is outside the supported limits).
+// candidates the passes enumerate (every product of an entry on an unsorted B
+// row, only the kept prefix on a sorted one), or -1 if the row is outside the
+// supported limits; *full_out receives the candidates before the filter.
 template <int RA>
-__device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* a0_out, int32_t* na_out) {
+__device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* a0_out, int32_t* na_out,
+                            int64_t* full_out) {
   const int tid = threadIdx.x;
   const int32_t a0 = g.A.row_ptr[i];
   const int32_t nA = g.A.row_ptr[i + 1] - a0;
@@ -97,7 +113,7 @@ __device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* 
   if (nA > RA) return -1;
   constexpr int kPer = RA / kSymThreads;
   int32_t len[kPer];
-  int64_t mysum = 0;
+  int64_t mysum = 0, myfull = 0;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int32_t p = tid * kPer + u;
@@ -105,15 +121,24 @@ __device__ int32_t load_row(const SymArgs& g, int32_t i, RowA<RA>& ra, int32_t* 
     if (p < nA) {
       const int32_t k = g.A.col_idx[a0 + p];
       const int32_t qs = g.B.row_ptr[k];
-      len[u] = g.B.row_ptr[k + 1] - qs;
+      const int32_t n = g.B.row_ptr[k + 1] - qs;
+      const double a = g.use_eps ? g.normA[a0 + p] : 0.0;
+      const bool srt = g.sorted_mode && g.bsorted[k];
+      len[u] = srt ? kept_prefix(g, a, qs, n) : n;
+      if (srt) g.akeep[a0 + p] = len[u];
+      myfull += n;
       ra.qs[p] = qs;
       ra.ks[p] = g.A.col_sizes[k];
-      ra.nrm[p] = g.use_eps ? g.normA[a0 + p] : 0.0;
+      ra.nrm[p] = a;
+      ra.srt[p] = srt ? 1 : 0;
     }
     mysum += len[u];
   }
-  int64_t total;
+  int64_t total, full;
   int64_t run = block_exclusive_scan<kSymThreads>(mysum, &total);
+  if (g.sorted_mode) (void)block_exclusive_scan<kSymThreads>(myfull, &full);  // uniform
+  else full = total;  // every candidate enumerated
+  *full_out = full;
   if (total > 0x7fffffffLL) return -1;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -149,6 +174,12 @@ __device__ __forceinline__ void candidate(const RowA<RA>& ra, int32_t nA, int32_
   *hint = lo;
   *p_out = lo;
   *q_out = ra.qs[lo] + (t - ra.pre[lo]);
+}
+
+// B block of the r-th enumerated candidate of an entry whose B row starts at
+// q0: the r-th block in norm order on a sorted row, else the r-th stored.
+__device__ __forceinline__ int32_t cand_block(const SymArgs& g, bool srt, int32_t q0, int32_t r) {
+  return srt ? g.bord[q0 + r] : q0 + r;
 }
 
 template <int RA>
@@ -215,7 +246,8 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
     }
     __syncthreads();
     int32_t a0, nA;
-    const int32_t T = load_row(g, i, ra, &a0, &nA);
+    int64_t full;
+    const int32_t T = load_row(g, i, ra, &a0, &nA, &full);
     if (T < 0) {
       if (DEFER) {
         if (tid == 0) g.huge[atomicAdd(g.n_huge, 1)] = i;
@@ -243,9 +275,14 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
       for (int u = 0; u < kCandBatch; ++u) {
         const int32_t t = tb + u * 64;
         int32_t p = 0, q = 0;
-        if (t < s1) candidate(ra, nA, t, &hint, &p, &q);
+        bool srt = false;
+        if (t < s1) {
+          candidate(ra, nA, t, &hint, &p, &q);
+          srt = ra.srt[p] != 0;
+          if (srt) q = g.bord[q];  // a kept candidate by construction
+        }
         pp[u] = p;
-        kk[u] = t < s1 && keep_product(g, ra, p, q);
+        kk[u] = t < s1 && (srt || keep_product(g, ra, p, q));
         jj[u] = t < s1 ? g.B.col_idx[q] : 0;
       }
 #pragma unroll
@@ -292,7 +329,7 @@ __device__ void count_row(const SymArgs& g, int32_t i, CountShared<RA, HB>& sh) 
         g.row_nc[i] = bad ? 0 : s_nc;
         g.row_np[i] = bad ? 0 : (int64_t)s_np;
         g.row_nv[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_sumn;
-        g.row_ncand[i] = T;
+        g.row_ncand[i] = full;
         g.row_nf[i] = bad ? 0 : (int64_t)g.c_row_sizes[i] * (int64_t)s_nf;
         // the fill forms beyond the tiny one this row needs (few rows do)
         if (DEFER && !bad && (nA > kTinyRowA || s_nc > kTinyRowC))
@@ -538,8 +575,9 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_count_huge(SymArgs g) {
 template <int RA>
 struct RowFill {
   int32_t qs[RA];        // first B block of B row k_p
-  int32_t pre[RA + 1];   // exclusive prefix of B row lengths
+  int32_t pre[RA + 1];   // exclusive prefix of the enumerated candidates per entry
   double nrm[RA];        // norm of A(i, k_p)
+  int8_t srt[RA];        // B row k_p enumerated in norm order (its kept prefix only)
 };
 
 // Capacities of one form of the fill pass: 2^HB hash slots, at most RA
@@ -582,9 +620,12 @@ __device__ int32_t load_row_fill(const SymArgs& g, int32_t i, RowFill<RA>& ra, i
     if (p < nA) {  // nA <= RA
       const int32_t k = g.A.col_idx[a0 + p];
       const int32_t qs = g.B.row_ptr[k];
-      len[u] = g.B.row_ptr[k + 1] - qs;
+      const bool srt = g.sorted_mode && g.bsorted[k];
+      // the count pass left a sorted entry's kept prefix in akeep
+      len[u] = srt ? g.akeep[a0 + p] : g.B.row_ptr[k + 1] - qs;
       ra.qs[p] = qs;
       ra.nrm[p] = g.use_eps ? g.normA[a0 + p] : 0.0;
+      ra.srt[p] = srt ? 1 : 0;
     }
     mysum += len[u];
   }
@@ -697,8 +738,9 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
       for (int u = 0; u < kCandBatch; ++u) {
         const int32_t t = tb + u * 64;
         const int32_t p = t < s1 ? (hint = fill_entry_from(ra, nA, hint, t)) : 0;
-        const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-        kk[u] = t < s1 && fill_keep(g, ra, p, q);
+        const bool srt = ra.srt[p] != 0;
+        const int32_t q = t < s1 ? cand_block(g, srt, ra.qs[p], t - ra.pre[p]) : 0;
+        kk[u] = t < s1 && (srt || fill_keep(g, ra, p, q));
         jj[u] = t < s1 ? g.B.col_idx[q] : 0;
       }
 #pragma unroll
@@ -799,8 +841,9 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
           for (int u = 0; u < kCandBatch; ++u) {
             const int32_t t = tb + u * 64;
             const int32_t p = t < c1 ? (chint = fill_entry_from(ra, nA, chint, t)) : 0;
-            const int32_t q = ra.qs[p] + (t - ra.pre[p]);
-            kk[u] = t < c1 && fill_keep(g, ra, p, q);
+            const bool srt = ra.srt[p] != 0;
+            const int32_t q = t < c1 ? cand_block(g, srt, ra.qs[p], t - ra.pre[p]) : 0;
+            kk[u] = t < c1 && (srt || fill_keep(g, ra, p, q));
             jj[u] = t < c1 ? g.B.col_idx[q] : 0;
           }
 #pragma unroll
@@ -840,7 +883,7 @@ __device__ void fill_row(const SymArgs& g, int32_t i, FillShared<Cap>& sh) {
             const int32_t p = rh;
             const uint32_t below = rmask[r] & ((1u << (p - r0)) - 1u);
             const int32_t pos = spre[r] + cursor[r] + __builtin_popcount(below);
-            g.prod[prow + pos] = make_int2(a0 + p, ra.qs[p] + (t - ra.pre[p]));
+            g.prod[prow + pos] = make_int2(a0 + p, cand_block(g, ra.srt[p] != 0, ra.qs[p], t - ra.pre[p]));
           }
         }
         __syncthreads();
@@ -920,6 +963,69 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_fill_huge(SymArgs g) {
     fill_row<FillHuge>(g, i, sh);
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ norm order
+
+// One workgroup per B block row (grid-strided): a bitonic sort in LDS of the
+// row's (norm, block) pairs into descending norm, ties by ascending block, the
+// row padded to a power of two with entries that sort last.  A row of more
+// than kSortRow blocks keeps its stored order (bsorted[k] = 0).
+__global__ __launch_bounds__(256) void k_sort_row_norms(MatView B, const double* __restrict__ normB,
+                                                        int32_t* __restrict__ bord, double* __restrict__ bnrm,
+                                                        uint8_t* __restrict__ bsorted) {
+  __shared__ double key[kSortRow];
+  __shared__ int32_t idx[kSortRow];
+  const int tid = threadIdx.x;
+  for (int32_t k = blockIdx.x; k < B.nbrows; k += gridDim.x) {
+    const int32_t q0 = B.row_ptr[k], n = B.row_ptr[k + 1] - q0;  // uniform over the workgroup
+    if (n > kSortRow) {
+      if (tid == 0) bsorted[k] = 0;
+      continue;
+    }
+    int32_t m = 1;
+    while (m < n) m <<= 1;
+    for (int32_t x = tid; x < m; x += 256) {
+      key[x] = x < n ? normB[q0 + x] : -1.0;  // norms are >= 0: padding sorts last
+      idx[x] = x < n ? q0 + x : 0x7fffffff;
+    }
+    __syncthreads();
+    for (int32_t size = 2; size <= m; size <<= 1) {
+      for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int32_t x = tid; x < m; x += 256) {
+          const int32_t y = x ^ stride;
+          if (y > x) {
+            // y before x in the final order: larger norm, or equal norm and smaller block
+            const bool y_first = key[y] > key[x] || (key[y] == key[x] && idx[y] < idx[x]);
+            const bool forward = (x & size) == 0;  // this run ends in final order
+            if (y_first == forward) {
+              const double tk = key[x];
+              key[x] = key[y];
+              key[y] = tk;
+              const int32_t ti = idx[x];
+              idx[x] = idx[y];
+              idx[y] = ti;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int32_t x = tid; x < n; x += 256) {
+      bord[q0 + x] = idx[x];
+      bnrm[q0 + x] = key[x];
+    }
+    if (tid == 0) bsorted[k] = 1;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort_row_norms(const MatView& B, const double* normB, int32_t* bord, double* bnrm,
+                                 uint8_t* bsorted, hipStream_t s) {
+  if (B.nbrows <= 0) return hipSuccess;
+  const int grid = B.nbrows < 65536 ? B.nbrows : 65536;
+  hipLaunchKernelGGL(k_sort_row_norms, dim3(grid), dim3(256), 0, s, B, normB, bord, bnrm, bsorted);
+  return hipGetLastError();
 }
 
 hipError_t launch_sym_count(const SymArgs& a, hipStream_t s) {
