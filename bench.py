@@ -135,6 +135,10 @@ def sweep_leg(steps, warmup, working_set=2 << 30):
         dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, stream)
         # the autotuner picks the small-block variant for this edge (untimed)
         variants = bsmm.bsmm_tune_small(1.0, dA.handle, dB.handle, 1.0, dCin.handle, dC.handle, 0.0, 2, stream)[0]
+        # and the tile shape and form of the generic path (untimed)
+        midv, mid_ms = bsmm.bsmm_tune_mid(1.0, dA.handle, dB.handle, 1.0, dCin.handle, dC.handle, 0.0, 2, stream)
+        if midv >= 0:
+            variants = [midv]
         for _ in range(warmup):
             bsmm.multiply(1.0, dA, dB, 1.0, dCin, dC, 0.0, stream=stream)
         torch.cuda.synchronize()
@@ -546,6 +550,19 @@ def main():
     def step():
         bsmm.multiply(w.alpha, dA, dB, w.beta, dCin, dC, w.eps, stream=stream)
 
+    mid_tune = None
+    if args.workload == "mixed_dense":
+        # the autotuner picks the generic path's tile shape and form for these
+        # block edges before the timed steps (the tuning is not timed)
+        midv, mid_ms = bsmm.bsmm_tune_mid(w.alpha, dA.handle, dB.handle, w.beta,
+                                          dCin.handle if dCin is not None else None, dC.handle, w.eps, 5, stream)
+        if midv >= 0:
+            mid_tune = {"variant": midv, "t16": bool(midv & 1), "matrix_cores": bool(midv & 2),
+                        "ms_per_launch": [round(x / 5, 5) for x in mid_ms.tolist()],
+                        "note": "variant bit 0: one 16x16 sub-tile for C blocks with both edges <= 16; bit 1: FP64 matrix-core form "
+                                "(0 ms: not allowed for these inner edges)"}
+            log(f"[bench] generic path tuned: {mid_tune}")
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -602,6 +619,8 @@ def main():
         sl = out["slice_int8x7"]
         log(f"[bench] slice: {sl['ms_per_step']} ms/step ({sl['speedup_vs_fp64']}x), rel Frobenius error "
             f"{sl['rel_frobenius_vs_fp64']:.2e}")
+    if mid_tune is not None:
+        out["mid_tune"] = mid_tune
     if args.workload == "water":
         log("[bench] per shape class timing of the small-block kernel")
         out["small_classes"] = small_class_leg(w, dA, dB, dCin, dC, stream)

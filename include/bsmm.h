@@ -87,6 +87,9 @@ enum {
 /* Number of compiled pipeline variants of the small-block path. */
 #define BSMM_SMALL_VARIANTS 8
 
+/* Number of variants of the generic path (bsmm_tune_mid). */
+#define BSMM_MID_VARIANTS 4
+
 /* Counters of the last multiply that wrote a handle. */
 typedef struct {
   int64_t candidates;  /* block products with both blocks present (before the filter) */
@@ -95,8 +98,9 @@ typedef struct {
   int64_t nvals;       /* values in the result */
   double useful_flops; /* sum over kept products of 2*m*n*k */
   int32_t path;        /* BSMM_PATH_* */
-  int32_t variants[4]; /* small-block variant used per shape class 8x8, 8x16, 16x8, 16x16
-                          (-1 on other paths) */
+  int32_t variants[4]; /* small-block variant used per shape class 8x8, 8x16, 16x8, 16x16;
+                          on the generic path {variant, -1, -1, -1} (bsmm_tune_mid);
+                          -1 on the 23x23 paths */
   int32_t panels;      /* stack panels the products were built and consumed in (1: whole stack) */
 } bsmm_mult_stats;
 
@@ -280,6 +284,55 @@ bsmm_status bsmm_tune_get(uint64_t key, int32_t* variants);
  * variants[4*cap] (host arrays); *n receives the number of entries in the
  * table. */
 bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, int32_t* n);
+
+/*
+ * Autotuner of the generic path (blocks that are neither all <= 16 nor all
+ * 23x23; Section 2: the batched multiply is tuned for each set of block
+ * dimensions).  The path cuts every C block into square sub-tiles and
+ * accumulates one sub-tile per wave over K chunks of 32.  A variant fixes the
+ * tile shape and the form:
+ *   bit 0 (tile policy): 0 = 32x32 sub-tiles for every C block; 1 = one
+ *          16x16 sub-tile, on the vector units, for each C block with both
+ *          edges <= 16 (a 9x9 block beside 22- and 32-edge blocks pads to
+ *          16x16 instead of 32x32);
+ *   bit 1 (form): the FP64 matrix cores (v_mfma_f64_4x4x4_4b) for 32x32
+ *          sub-tiles of C blocks with both edges >= 16; only allowed when
+ *          every inner block edge is >= 16, and dropped otherwise.
+ * The table maps the block edges present (A's rows, A's columns, B's
+ * columns, each as a mask with bit e-1 set for edge e and bit 31 for every
+ * edge >= 32) to a variant; a multiply whose masks have no entry uses 2 when
+ * every inner edge is >= 16, else 0.  The vector form gives the same bits
+ * with either tile policy; the matrix-core form adds in another order, within
+ * FP64 rounding of the exact sum.
+ *
+ * bsmm_tune_mid computes C_out = alpha*A*B + beta*C_in exactly as
+ * bsmm_multiply with BSMM_FP64 does, then, if the generic path served it,
+ * times the numeric phase with every allowed variant (`reps` launches each,
+ * HIP events on `stream`), enters the fastest into the table and leaves C_out
+ * as that variant computes it.  Arguments as bsmm_tune_small, except:
+ *   variant_out : host int32: the chosen variant, or -1 when another path
+ *                 serves these sizes (nothing is timed, the table unchanged)
+ *   ms_out      : NULL, or host array [BSMM_MID_VARIANTS]: milliseconds of
+ *                 each variant summed over the reps (0 if not allowed)
+ * Synchronises `stream`.
+ */
+bsmm_status bsmm_tune_mid(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C_out,
+                          double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream);
+
+/* Key of the product A*B in the generic path's table: masks[3] (host) =
+ * {A's row edges, A's column edges, B's column edges}, as described above. */
+bsmm_status bsmm_mid_key(bsmm_mat A, bsmm_mat B, uint32_t* masks);
+
+/* Table entry of masks[3]: bsmm_mid_set enters `variant`
+ * (0 .. BSMM_MID_VARIANTS-1) or removes the entry (variant -1); bsmm_mid_get
+ * writes the entry into *variant, -1 if there is none.  Process-wide, guarded
+ * by the same lock as the small-block table. */
+bsmm_status bsmm_mid_set(const uint32_t* masks, int32_t variant);
+bsmm_status bsmm_mid_get(const uint32_t* masks, int32_t* variant);
+
+/* Copy up to `cap` entries of the generic path's table into masks[3*cap] and
+ * variants[cap] (host arrays); *n receives the number of entries. */
+bsmm_status bsmm_mid_entries(uint32_t* masks, int32_t* variants, int32_t cap, int32_t* n);
 
 /*
  * Graph-capturable mode.  Reserve device capacity in m for the results of the

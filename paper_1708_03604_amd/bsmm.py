@@ -30,6 +30,7 @@ BSMM_PATH_SMALL = 2
 BSMM_PATH_SPLIT23 = 3
 BSMM_PATH_SLICE23 = 4
 BSMM_SMALL_VARIANTS = 8
+BSMM_MID_VARIANTS = 4
 
 
 class BsmmError(RuntimeError):
@@ -75,6 +76,11 @@ SIGNATURES = {
     "bsmm_tune_set": ([_u64, _vp], _int),
     "bsmm_tune_get": ([_u64, _vp], _int),
     "bsmm_tune_entries": ([_vp, _vp, _i32, _vp], _int),
+    "bsmm_tune_mid": ([_dbl, _vp, _vp, _dbl, _vp, _vp, _dbl, _i32, _vp, _vp, _vp], _int),
+    "bsmm_mid_key": ([_vp, _vp, _vp], _int),
+    "bsmm_mid_set": ([_vp, _i32], _int),
+    "bsmm_mid_get": ([_vp, _vp], _int),
+    "bsmm_mid_entries": ([_vp, _vp, _i32, _vp], _int),
 }
 
 _lib = None
@@ -301,6 +307,51 @@ def bsmm_tune_entries():
     vs = np.zeros((max(n.value, 1), 4), dtype=np.int32)
     _check("bsmm_tune_entries", lib().bsmm_tune_entries(keys.ctypes.data, vs.ctypes.data, n.value, ctypes.byref(n)))
     return {k: v.tolist() for k, v in zip(keys[:n.value].tolist(), vs[:n.value])}
+
+
+def bsmm_tune_mid(alpha, A, B, beta, C_in, C_out, filter_eps, reps=5, stream=None):
+    """Returns (chosen variant of the generic path, -1 if another path serves
+    the sizes; milliseconds per variant [BSMM_MID_VARIANTS])."""
+    v = ctypes.c_int32()
+    ms = np.zeros(BSMM_MID_VARIANTS, dtype=np.float64)
+    _check("bsmm_tune_mid", lib().bsmm_tune_mid(float(alpha), A, B, float(beta), C_in, C_out, float(filter_eps),
+                                                int(reps), ctypes.byref(v), ms.ctypes.data, _stream(stream)))
+    return v.value, ms
+
+
+def _masks(masks):
+    m = np.ascontiguousarray(masks, dtype=np.uint32)
+    if m.shape != (3,):
+        raise ValueError("three edge masks: A rows, A columns, B columns")
+    return m
+
+
+def bsmm_mid_key(A, B):
+    m = np.zeros(3, dtype=np.uint32)
+    _check("bsmm_mid_key", lib().bsmm_mid_key(A, B, m.ctypes.data))
+    return tuple(int(x) for x in m)
+
+
+def bsmm_mid_set(masks, variant):
+    """Enter `variant` for the edge masks, or remove the entry (variant -1 or None)."""
+    m = _masks(masks)
+    _check("bsmm_mid_set", lib().bsmm_mid_set(m.ctypes.data, -1 if variant is None else int(variant)))
+
+
+def bsmm_mid_get(masks):
+    m = _masks(masks)
+    v = ctypes.c_int32()
+    _check("bsmm_mid_get", lib().bsmm_mid_get(m.ctypes.data, ctypes.byref(v)))
+    return v.value
+
+
+def bsmm_mid_entries():
+    n = ctypes.c_int32()
+    _check("bsmm_mid_entries", lib().bsmm_mid_entries(None, None, 0, ctypes.byref(n)))
+    ms = np.zeros((max(n.value, 1), 3), dtype=np.uint32)
+    vs = np.zeros(max(n.value, 1), dtype=np.int32)
+    _check("bsmm_mid_entries", lib().bsmm_mid_entries(ms.ctypes.data, vs.ctypes.data, n.value, ctypes.byref(n)))
+    return {tuple(int(x) for x in m): int(v) for m, v in zip(ms[:n.value], vs[:n.value])}
 
 
 # ------------------------------------------------------------ convenience

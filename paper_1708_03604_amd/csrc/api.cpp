@@ -154,6 +154,7 @@ struct bsmm_matrix {
   DBuf<int64_t> class_cnt, class_pre, class_np, class_q;
   DBuf<int32_t> class_start;
   NumArgs small_args{};  // arguments of the last small-block launch (re-launched by the tuner)
+  NumArgs mid_args{};    // arguments of the last generic-path launch (re-launched by the tuner)
   int64_t* h_totals = nullptr;  // pinned, kPinned entries
   // phase timing: 7 events per recorded multiply
   bool timing = false;
@@ -325,6 +326,30 @@ ClassVariants tuned_variants(uint64_t key, int32_t edge) {
   for (auto& x : v)
     if (edge > small_variant_max_edge(x)) x = kSmallDefault;
   return v;
+}
+
+// Tuning table of the generic path: edge masks (A's rows, A's columns, B's
+// columns) -> variant (bit 0: one 16x16 sub-tile for C blocks with both
+// edges <= 16; bit 1: the matrix-core form where every inner edge is >= 16).
+using MidKey = std::array<uint32_t, 3>;
+std::map<MidKey, int32_t> g_tune_mid;
+
+MidKey mid_key(const bsmm_matrix* A, const bsmm_matrix* B) { return {A->row_edges, A->col_edges, B->col_edges}; }
+
+bool mid_wide(const bsmm_matrix* A) { return (A->col_edges & 0x7fffu) == 0; }  // no inner block edge below 16
+
+// Variant of the generic path for A*B: the table entry, else the untuned
+// choice (32x32 sub-tiles, the matrix-core form where allowed); bit 1 is
+// dropped when an inner edge is below 16.
+int32_t mid_variant(const bsmm_matrix* A, const bsmm_matrix* B) {
+  const bool wide = mid_wide(A);
+  int32_t v = wide ? 2 : 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_mid.find(mid_key(A, B));
+    if (it != g_tune_mid.end()) v = it->second;
+  }
+  return wide ? v : (v & 1);
 }
 
 struct EventPair {
@@ -888,7 +913,9 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   na.c_old_idx = C->old_idx.p;
   na.prod = C->prod.p;
   na.c_values = out.values.p;
-  na.wide_inner = (A->col_edges & 0x7fffu) == 0;  // no inner block edge below 16
+  const int32_t midv = mid_variant(A, B);
+  na.wide_inner = (midv >> 1) & 1;
+  na.mid_t16 = midv & 1;
   na.uniform = uniform;
   na.c_row_ptr = out.row_ptr.p;
   ClassVariants variants{-1, -1, -1, -1};
@@ -923,8 +950,10 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
       C->small_args = na;
     } else {
       HIP_W(launch_numeric(na, uniform, C->work.p, s));
+      if (uniform != 23) variants = {midv, -1, -1, -1};
     }
   }
+  if (!small && uniform != 23) C->mid_args = na;
   mark(C, ev, 5, s);
   HIP_W(launch_finish_multiply(C->totals.p, out.values.p, C->dsz.p, s));
   mark(C, ev, 6, s);
@@ -1278,6 +1307,106 @@ bsmm_status bsmm_tune_small(double alpha, bsmm_mat A, bsmm_mat B, double beta, b
   }
   std::copy(best.begin(), best.end(), C->stats.variants);
   std::copy(best.begin(), best.end(), variants_out);
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_tune_mid(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsmm_mat C_in, bsmm_mat C,
+                          double filter_eps, int32_t reps, int32_t* variant_out, double* ms_out, void* stream) {
+  g_err.clear();
+  if (!variant_out) return fail(BSMM_E_ARG, "NULL variant_out");
+  if (reps < 1 || reps > 1000) return fail(BSMM_E_ARG, "reps must be in 1 .. 1000");
+  if (C && C == C_in && beta != 0.0) return fail(BSMM_E_ARG, "tuning needs C_in distinct from C_out");
+  if (C && C->cap_nnzb > 0) return fail(BSMM_E_ARG, "tuning does not take a reserved output");
+  bsmm_status st = bsmm_multiply(alpha, A, B, beta, C_in, C, filter_eps, BSMM_FP64, stream);
+  if (st != BSMM_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  *variant_out = -1;
+  if (ms_out) std::fill(ms_out, ms_out + BSMM_MID_VARIANTS, 0.0);
+  if (C->stats.path != BSMM_PATH_GENERIC) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return BSMM_OK;
+  }
+  // Each launch recomputes C_out's values from A, B and C_in (never from
+  // C_out itself), so repeated launches leave the same result.
+  NumArgs na = C->mid_args;
+  EventPair ev;
+  HIP_TRY(hipEventCreate(&ev.e[0]));
+  HIP_TRY(hipEventCreate(&ev.e[1]));
+  const bool wide = mid_wide(A);
+  double best_ms = HUGE_VAL;
+  int32_t best = 0;
+  for (int32_t v = 0; v < BSMM_MID_VARIANTS; ++v) {
+    if ((v & 2) && !wide) continue;  // the matrix-core form needs inner edges >= 16: not timed
+    na.wide_inner = (v >> 1) & 1;
+    na.mid_t16 = v & 1;
+    HIP_TRY(hipEventRecord(ev.e[0], s));
+    for (int32_t r = 0; r < reps; ++r) HIP_TRY(launch_numeric(na, 0, C->work.p, s));
+    HIP_TRY(hipEventRecord(ev.e[1], s));
+    HIP_TRY(hipEventSynchronize(ev.e[1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    if (ms_out) ms_out[v] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  na.wide_inner = (best >> 1) & 1;
+  na.mid_t16 = best & 1;
+  HIP_TRY(launch_numeric(na, 0, C->work.p, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_mid[mid_key(A, B)] = best;
+  }
+  C->mid_args = na;
+  C->stats.variants[0] = best;
+  *variant_out = best;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_mid_key(bsmm_mat A, bsmm_mat B, uint32_t* masks) {
+  g_err.clear();
+  if (!A || !B || !masks) return fail(BSMM_E_ARG, "NULL argument");
+  const MidKey k = mid_key(A, B);
+  std::copy(k.begin(), k.end(), masks);
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_mid_set(const uint32_t* masks, int32_t variant) {
+  g_err.clear();
+  if (!masks) return fail(BSMM_E_ARG, "NULL masks");
+  if (variant < -1 || variant >= BSMM_MID_VARIANTS) return fail(BSMM_E_ARG, "variant out of range");
+  const MidKey k{masks[0], masks[1], masks[2]};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (variant < 0)
+    g_tune_mid.erase(k);
+  else
+    g_tune_mid[k] = variant;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_mid_get(const uint32_t* masks, int32_t* variant) {
+  g_err.clear();
+  if (!masks || !variant) return fail(BSMM_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_mid.find(MidKey{masks[0], masks[1], masks[2]});
+  *variant = it == g_tune_mid.end() ? -1 : it->second;
+  return BSMM_OK;
+}
+
+bsmm_status bsmm_mid_entries(uint32_t* masks, int32_t* variants, int32_t cap, int32_t* n) {
+  g_err.clear();
+  if (!n || cap < 0 || (cap > 0 && (!masks || !variants))) return fail(BSMM_E_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int32_t i = 0;
+  for (const auto& kv : g_tune_mid) {
+    if (i >= cap) break;
+    std::copy(kv.first.begin(), kv.first.end(), masks + 3 * i);
+    variants[i] = kv.second;
+    ++i;
+  }
+  *n = (int32_t)g_tune_mid.size();
   return BSMM_OK;
 }
 

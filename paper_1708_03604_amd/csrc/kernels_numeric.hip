@@ -13,9 +13,20 @@ namespace bsmm {
 
 // ---------------------------------------------------------------------------
 // Any block sizes (the path for blocks that are neither all <= 16 nor all
-// 23x23): one wave per C block at a time.  The C block is cut into 32x32
-// sub-tiles and every product into K chunks of at most 32; a sub-tile is
-// accumulated in registers over all chunks of all products of its C block.
+// 23x23): one wave per C block at a time.  The C block is cut into square
+// sub-tiles of edge T (32, or 16 where the tile policy asks for it) and every
+// product into K chunks of at most 32; a sub-tile is accumulated in registers
+// over all chunks of all products of its C block.
+//
+// Tile policy (g.mid_t16, chosen by the autotuner per set of block edges):
+// 0 = every C block in 32x32 sub-tiles; 1 = a C block with both edges <= 16
+// (e.g. 9x9 beside 22- and 32-edge blocks) is one 16x16 sub-tile, in the
+// vector form, lane 8*ty + tx owning rows 2ty, 2ty+1 and columns 2tx, 2tx+1,
+// with half the operand loads per chunk and a quarter of the FMAs.  (Cutting
+// larger blocks into 16x16 sub-tiles too, wherever that pads less, measured
+// slower: every extra sub-tile walks the block's products again.)  Both sizes
+// sum every output over the same inner indices in the same order with the
+// same FMAs, so the vector form gives the same bits with either.
 //
 // A chunk is staged through wave-private LDS with a row stride of kMidStride
 // doubles, zeros past the block and the chunk; the loads of the next chunk
@@ -45,7 +56,7 @@ constexpr int kMidOperand = kMid * kMidStride;
 // Position of a wave in its chunk sequence: C block c, sub-tile (ti, tj),
 // product x in [x0, x1), K chunk k0 of the product's inner size k.
 struct MidCursor {
-  int32_t c, m, n, ti, tj, nti, ntj, k, k0;
+  int32_t c, m, n, t, ti, tj, nti, ntj, k, k0;
   int64_t x, x0, x1, aoff, boff;
   bool valid;
 };
@@ -70,8 +81,9 @@ __device__ __forceinline__ void mid_block(const NumArgs& g, MidCursor& u, int32_
   const int64_t off = g.c_blk_off[u.c];
   u.n = g.c_col_sizes[g.c_col_idx[u.c]];
   u.m = (int32_t)((uint32_t)(g.c_blk_off[u.c + 1] - off) / (uint32_t)u.n);
-  u.nti = (u.m + kMid - 1) / kMid;
-  u.ntj = (u.n + kMid - 1) / kMid;
+  u.t = (g.mid_t16 && u.m <= 16 && u.n <= 16) ? 16 : kMid;
+  u.nti = (u.m + u.t - 1) / u.t;
+  u.ntj = (u.n + u.t - 1) / u.t;
   u.ti = 0;
   u.tj = 0;
   u.x0 = g.prod_ptr[u.c];
@@ -122,14 +134,29 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
   mid_block(g, f, nnzc);
   if (!f.valid) return;
 
-  // Operand registers of the chunk in flight: A(32ti + lr + 2v, k0 + lc) and
-  // B(k0 + lr + 2v, 32tj + lc), zero outside the block and the chunk.
+  // Operand registers of the chunk in flight, zero outside the block and the
+  // chunk: with 32x32 sub-tiles A(32ti + lr + 2v, k0 + lc) and
+  // B(k0 + lr + 2v, 32tj + lc), v < 16; with 16x16 sub-tiles
+  // A(16ti + lr + 2v, k0 + lc) and B(k0 + br + 4v, 16tj + bc), v < 8.
   double ra[16], rb[16];
+  const int bc = lane & 15, br = lane >> 4;
   auto fetch = [&](const MidCursor& u) {
     const int kk = min(kMid, u.k - u.k0);
-    const int mm = min(kMid, u.m - kMid * u.ti), nn = min(kMid, u.n - kMid * u.tj);
-    const double* ap = g.A.values + u.aoff + (int64_t)(kMid * u.ti + lr) * u.k + u.k0 + lc;
-    const double* bp = g.B.values + u.boff + (int64_t)(u.k0 + lr) * u.n + kMid * u.tj + lc;
+    const int mm = min(u.t, u.m - u.t * u.ti), nn = min(u.t, u.n - u.t * u.tj);
+    if (u.t == 16) {
+      const double* ap = g.A.values + u.aoff + (int64_t)(16 * u.ti + lr) * u.k + u.k0 + lc;
+      const double* bp = g.B.values + u.boff + (int64_t)(u.k0 + br) * u.n + 16 * u.tj + bc;
+      const bool acol = lc < kk, bcol = bc < nn;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int r = lr + 2 * v;
+        ra[v] = (acol && r < mm) ? ap[(int64_t)2 * v * u.k] : 0.0;
+        rb[v] = (bcol && br + 4 * v < kk) ? bp[(int64_t)4 * v * u.n] : 0.0;
+      }
+      return;
+    }
+    const double* ap = g.A.values + u.aoff + (int64_t)(u.t * u.ti + lr) * u.k + u.k0 + lc;
+    const double* bp = g.B.values + u.boff + (int64_t)(u.k0 + lr) * u.n + u.t * u.tj + lc;
     const bool acol = lc < kk, bcol = lc < nn;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -138,8 +165,16 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
       rb[v] = (bcol && r < kk) ? bp[(int64_t)2 * v * u.n] : 0.0;
     }
   };
-  auto stage = [&](bool mma) {
-    if (mma) {
+  auto stage = [&](bool mma, bool t16) {
+    if (t16) {
+      // B first: were the A stores (the vector form's first eight) first,
+      // the compiler would merge the two loops into one of run-time length
+      // and keep ra in scratch memory
+#pragma unroll
+      for (int v = 0; v < 8; ++v) Bs[(br + 4 * v) * kMidStride + bc] = rb[v];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) As[lc * kMidStride + lr + 2 * v] = ra[v];
+    } else if (mma) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         As[(lr + 2 * v) * kMidStride + lc] = ra[v];
@@ -168,9 +203,10 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
   for (;;) {
     // the chunk to multiply now is the one the fetch cursor points at
     const MidCursor cur = f;
-    const bool mma = WIDE && cur.m >= 16 && cur.n >= 16;  // uniform over the wave
+    const bool mma = WIDE && cur.t == kMid && cur.m >= 16 && cur.n >= 16;  // uniform over the wave
+    const bool t16 = cur.t == 16;
     sync();
-    stage(mma);
+    stage(mma, t16);
     sync();
     const bool last = mid_next(g, f, nnzc, nwaves);
     if (f.valid) fetch(f);
@@ -194,6 +230,19 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
         for (int I = 0; I < 4; ++I)
 #pragma unroll
           for (int J = 0; J < 4; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[I].y, b[J].y, acc[I][J], 0, 0, 0);
+      }
+    } else if (t16) {
+      // 16x16 sub-tile: acc[i][j] for i, j < 2 (rows 2ty + i, columns 2tx + j)
+      const double* ap = As + 2 * ty;
+      const double* bp = Bs + 2 * tx;
+#pragma unroll 4
+      for (int t = 0; t < kk; ++t) {
+        const double2 a = *reinterpret_cast<const double2*>(ap + t * kMidStride);
+        const double2 b = *reinterpret_cast<const double2*>(bp + t * kMidStride);
+        acc[0][0] = fma(a.x, b.x, acc[0][0]);
+        acc[0][1] = fma(a.x, b.y, acc[0][1]);
+        acc[1][0] = fma(a.y, b.x, acc[1][0]);
+        acc[1][1] = fma(a.y, b.y, acc[1][1]);
       }
     } else {
       const double* ap = As + 4 * ty;
@@ -223,9 +272,9 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
         for (int j = 0; j < 4; ++j) {
           // matrix-core form: lane 16k + 4b + i' holds row 8I + 4(b >> 1) + k,
           // column 8J + 4(b & 1) + i' of super-tile (I, J) = (i, j)
-          const int r = kMid * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : 4 * ty + i);
-          const int cc = kMid * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : 4 * tx + j);
-          if (r < cur.m && cc < cur.n) {
+          const int r = cur.t * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : t16 ? 2 * ty + i : 4 * ty + i);
+          const int cc = cur.t * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : t16 ? 2 * tx + j : 4 * tx + j);
+          if ((!t16 || (i < 2 && j < 2)) && r < cur.m && cc < cur.n) {
             const int64_t e = (int64_t)r * cur.n + cc;
             double v = g.alpha * acc[i][j];
             if (ov) v = v + g.beta * ov[e];

@@ -1,4 +1,4 @@
-"""Autotuner of the small-block path and its table.
+"""Autotuners of the small-block and generic paths and their table.
 
 The small-block kernel pads every block to one of four shape classes
 (8 or 16 rows by 8 or 16 columns); a variant fixes per class the form of the
@@ -16,6 +16,17 @@ The table is saved as JSON, one entry per edge set:
       "ms": [...]}]}
 
 (`depths[c]` is bsmm_small_variant(variants[c])[c].)
+
+The generic path (blocks neither all <= 16 nor all 23x23) has its own
+variants (bsmm_tune_mid: 32x32 sub-tiles, or one 16x16 sub-tile for C
+blocks with both edges <= 16, and the FP64 vector or matrix-core form), kept
+per set of block edges under "mid_entries":
+
+    {"masks": [rows, inner, cols], "rows": [9, 22, 32], ..., "variant": 1,
+     "ms": [...]}
+
+(the masks have bit e-1 set for edge e, bit 31 for every edge >= 32; the
+edge lists show them, 32 standing for ">= 32").
 
 `load()` enters a saved table into the library; the package loads
 tune_gfx950.json next to this file, if present, when the library is first
@@ -63,19 +74,39 @@ def tune(alpha, A, B, beta, C_in, C_out, eps, reps=5, stream=None):
             "ms": [[round(x / reps, 5) for x in r] for r in ms.tolist()]}
 
 
+def mask_edges(mask):
+    """Edge mask of the generic path's key -> edges (32 stands for >= 32)."""
+    return [e + 1 for e in range(32) if (int(mask) >> e) & 1]
+
+
+def tune_mid(alpha, A, B, beta, C_in, C_out, eps, reps=5, stream=None):
+    """Tune the generic path on one product (Matrix wrappers); C_out receives
+    the product.  Returns the table entry (None if another path serves it)."""
+    v, ms = bsmm.bsmm_tune_mid(alpha, A.handle, B.handle, beta, C_in.handle if C_in is not None else None,
+                               C_out.handle, eps, reps, stream)
+    if v < 0:
+        return None
+    masks = bsmm.bsmm_mid_key(A.handle, B.handle)
+    return {"masks": list(masks), "rows": mask_edges(masks[0]), "inner": mask_edges(masks[1]),
+            "cols": mask_edges(masks[2]), "variant": int(v), "ms": [round(x / reps, 5) for x in ms.tolist()]}
+
+
 def load(path=TABLE):
-    """Enter a saved table into the library; returns its entries."""
+    """Enter a saved table into the library; returns its small-block entries."""
     with open(path) as f:
         table = json.load(f)
     entries = table.get("entries", [])
     for e in entries:
         bsmm.bsmm_tune_set(edges_key(e["rows"], e["inner"], e["cols"]), [int(x) for x in e["variants"]])
+    for e in table.get("mid_entries", []):
+        bsmm.bsmm_mid_set([int(x) for x in e["masks"]], int(e["variant"]))
     return entries
 
 
-def save(entries, path=TABLE, note=""):
+def save(entries, path=TABLE, note="", mid_entries=()):
     with open(path, "w") as f:
-        json.dump({"arch": "gfx950", "note": note, "entries": entries}, f, indent=1)
+        json.dump({"arch": "gfx950", "note": note, "entries": entries, "mid_entries": list(mid_entries)}, f,
+                  indent=1)
         f.write("\n")
 
 
@@ -102,8 +133,21 @@ def main():
         names.append(w.name)
         for m in (dA, dB, dC):
             m.close()
+    mid_entries = []
+    for w in (W.mixed_dense(),):
+        st = torch.cuda.Stream()
+        dA, dB, dCin = (bsmm.Matrix.from_csr(x, st) for x in (w.A, w.B, w.C_old))
+        dC = bsmm.Matrix.empty(w.A.row_sizes, w.B.col_sizes, st)
+        entry = tune_mid(w.alpha, dA, dB, w.beta, dCin, dC, w.eps, args.reps, st)
+        if entry is None:
+            raise SystemExit(f"the generic path does not serve {w.name}")
+        print(w.name, json.dumps(entry), flush=True)
+        mid_entries.append(entry)
+        names.append(w.name)
+        for m in (dA, dB, dCin, dC):
+            m.close()
     save(entries, args.out, note=f"tuned on {', '.join(names)}; {args.reps} launches per variant and class; "
-                                 "ms per launch")
+                                 "ms per launch", mid_entries=mid_entries)
 
 
 if __name__ == "__main__":

@@ -120,3 +120,32 @@ def test_tuning_table_json_roundtrip(tmp_path):
             bsmm.bsmm_tune_set(k, None)
         for k, v in saved.items():
             bsmm.bsmm_tune_set(k, v)
+
+
+def test_generic_path_table_without_device(tmp_path):
+    """The generic path's table (edge masks -> variant) and its JSON form."""
+    from paper_1708_03604_amd import tune
+    bsmm.lib()
+    saved = bsmm.bsmm_mid_entries()
+    key = (1 << 8 | 1 << 21 | 1 << 31, 1 << 8, 1 << 31)  # rows {9, 22, >=32}, inner {9}, cols {>=32}
+    try:
+        assert tune.mask_edges(key[0]) == [9, 22, 32]
+        bsmm.bsmm_mid_set(key, 1)
+        assert bsmm.bsmm_mid_get(key) == 1 and bsmm.bsmm_mid_entries()[key] == 1
+        for bad in (-2, bsmm.BSMM_MID_VARIANTS):
+            with pytest.raises(bsmm.BsmmError) as e:
+                bsmm.bsmm_mid_set(key, bad)
+            assert e.value.status == "BSMM_E_ARG"
+        bsmm.bsmm_mid_set(key, None)
+        assert bsmm.bsmm_mid_get(key) == -1 and key not in bsmm.bsmm_mid_entries()
+        mid = [{"masks": list(key), "rows": [9, 22, 32], "inner": [9], "cols": [32], "variant": 3, "ms": [1, 2, 0, 0]}]
+        path = str(tmp_path / "table.json")
+        tune.save([], path, note="test", mid_entries=mid)
+        assert tune.load(path) == []
+        assert bsmm.bsmm_mid_get(key) == 3
+    finally:
+        for k in bsmm.bsmm_mid_entries():
+            bsmm.bsmm_mid_set(k, None)
+        for k, v in saved.items():
+            bsmm.bsmm_mid_set(k, v)
+        assert bsmm.bsmm_mid_entries() == saved
