@@ -514,6 +514,8 @@ bsmm_status bsmm_destroy(bsmm_mat m) {
   m->class_start.release();
   m->dsz.release();
   m->frob_tmp.release();
+  m->huge.release();
+  m->panels.release();
   if (m->h_totals) (void)hipHostFree(m->h_totals);
   drop_events(m);
   delete m;
