@@ -168,3 +168,47 @@ def test_tuner_other_paths_and_errors(table):
     assert e.value.status == "BSMM_E_ARG"
     dS.close()
     dT.close()
+
+
+def test_tuned_variant_in_reserved_and_captured_multiplies(table):
+    """A reserved (device-sized) multiply takes the table's variant like an
+    eager one, and every replay of its captured graph gives the eager bits."""
+    import torch
+    A, B, Co = operands("mixed_9_22_32", 991)
+    ref = oracle.multiply(1.25, A, B, 0.5, Co, 0.0)
+    stream = torch.cuda.Stream()
+    dA, dB, dCin = (bsmm.Matrix.from_csr(x, stream) for x in (A, B, Co))
+    bsmm.bsmm_mid_set(bsmm.bsmm_mid_key(dA.handle, dB.handle), 1)
+    dE = bsmm.Matrix.empty(A.row_sizes, B.col_sizes, stream)
+    bsmm.multiply(1.25, dA, dB, 0.5, dCin, dE, 0.0, stream=stream)
+    eager = dE.to_host(stream)
+    assert bsmm.bsmm_stats(dE.handle)["variants"][0] == 1
+    assert rel_err(eager[2], ref.values) <= REL_TOL
+    nr, nc = len(A.row_sizes), len(B.col_sizes)
+    dR = bsmm.Matrix.empty(A.row_sizes, B.col_sizes, stream)
+    bsmm.bsmm_reserve(dR.handle, nr * nc, int(np.sum(A.row_sizes)) * int(np.sum(B.col_sizes)),
+                      nr * len(A.col_sizes) * nc, stream)
+    bsmm.multiply(1.25, dA, dB, 0.5, dCin, dR, 0.0, stream=stream)
+    got = dR.to_host(stream)
+    assert bsmm.bsmm_stats(dR.handle)["variants"][0] == 1
+    for r, g in zip(eager, got):
+        assert np.array_equal(r, g)
+    stream.synchronize()
+    bsmm.bsmm_capture_begin(stream)
+    try:
+        bsmm.multiply(1.25, dA, dB, 0.5, dCin, dR, 0.0, stream=stream)
+    finally:
+        graph = bsmm.bsmm_capture_end(stream)
+    try:
+        for _ in range(3):
+            bsmm.bsmm_graph_launch(graph, stream)
+            got = dR.to_host(stream)
+            for r, g in zip(eager, got):
+                assert np.array_equal(r, g)
+            # eager work between the replays
+            bsmm.multiply(1.0, dA, dB, 0.0, None, dE, 0.0, stream=stream)
+            stream.synchronize()
+    finally:
+        bsmm.bsmm_graph_destroy(graph)
+    for m in (dA, dB, dCin, dE, dR):
+        m.close()
