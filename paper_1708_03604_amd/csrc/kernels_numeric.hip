@@ -209,6 +209,26 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
     stage(mma, t16);
     sync();
     const bool last = mid_next(g, f, nnzc, nwaves);
+    // The sub-tile ends with this chunk: load its C_in values now, before the
+    // next chunk's operand loads, so that they arrive during the multiply and
+    // waiting for them at the finish does not wait for the operand loads.
+    double cin[4][4];
+    const int64_t off = last ? g.c_blk_off[cur.c] : 0;
+    if (last) {
+      const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
+      const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // matrix-core form: lane 16k + 4b + i' holds row 8I + 4(b >> 1) + k,
+          // column 8J + 4(b & 1) + i' of super-tile (I, J) = (i, j)
+          const int r = cur.t * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : t16 ? 2 * ty + i : 4 * ty + i);
+          const int cc = cur.t * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : t16 ? 2 * tx + j : 4 * tx + j);
+          const bool in = (!t16 || (i < 2 && j < 2)) && r < cur.m && cc < cur.n;
+          cin[i][j] = (ov && in) ? ov[(int64_t)r * cur.n + cc] : 0.0;
+        }
+    }
     if (f.valid) fetch(f);
     const int kk = max(0, min(kMid, cur.k - cur.k0));
     if (mma) {
@@ -263,22 +283,17 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
     }
     if (last) {
       // alpha * acc + beta * C_in, then store the lane's 16 outputs
-      const int64_t off = g.c_blk_off[cur.c];
-      const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
-      const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
+      const bool old = g.use_old && g.c_old_idx[cur.c] >= 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          // matrix-core form: lane 16k + 4b + i' holds row 8I + 4(b >> 1) + k,
-          // column 8J + 4(b & 1) + i' of super-tile (I, J) = (i, j)
           const int r = cur.t * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : t16 ? 2 * ty + i : 4 * ty + i);
           const int cc = cur.t * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : t16 ? 2 * tx + j : 4 * tx + j);
           if ((!t16 || (i < 2 && j < 2)) && r < cur.m && cc < cur.n) {
-            const int64_t e = (int64_t)r * cur.n + cc;
             double v = g.alpha * acc[i][j];
-            if (ov) v = v + g.beta * ov[e];
-            g.c_values[off + e] = v;
+            if (old) v = v + g.beta * cin[i][j];
+            g.c_values[off + (int64_t)r * cur.n + cc] = v;
           }
           acc[i][j] = 0.0;
         }
