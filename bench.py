@@ -558,9 +558,11 @@ def main():
                                           dCin.handle if dCin is not None else None, dC.handle, w.eps, 5, stream)
         if midv >= 0:
             mid_tune = {"variant": midv, "t16": bool(midv & 1), "matrix_cores": bool(midv & 2),
+                        "cin_prefetch": bool(midv & 4),
                         "ms_per_launch": [round(x / 5, 5) for x in mid_ms.tolist()],
-                        "note": "variant bit 0: one 16x16 sub-tile for C blocks with both edges <= 16; bit 1: FP64 matrix-core form "
-                                "(0 ms: not allowed for these inner edges)"}
+                        "note": "variant bit 0: one 16x16 sub-tile for C blocks with both edges <= 16; bit 1: FP64 "
+                                "matrix-core form (0 ms: not allowed for these inner edges); bit 2: C_in loaded before "
+                                "each sub-tile's last chunk"}
             log(f"[bench] generic path tuned: {mid_tune}")
 
     for _ in range(args.warmup):

@@ -88,7 +88,7 @@ enum {
 #define BSMM_SMALL_VARIANTS 8
 
 /* Number of variants of the generic path (bsmm_tune_mid). */
-#define BSMM_MID_VARIANTS 4
+#define BSMM_MID_VARIANTS 8
 
 /* Counters of the last multiply that wrote a handle. */
 typedef struct {
@@ -297,12 +297,15 @@ bsmm_status bsmm_tune_entries(uint64_t* keys, int32_t* variants, int32_t cap, in
  *          16x16 instead of 32x32);
  *   bit 1 (form): the FP64 matrix cores (v_mfma_f64_4x4x4_4b) for 32x32
  *          sub-tiles of C blocks with both edges >= 16; only allowed when
- *          every inner block edge is >= 16, and dropped otherwise.
+ *          every inner block edge is >= 16, and dropped otherwise;
+ *   bit 2 (C_in prefetch): a sub-tile's C_in values are loaded before its
+ *          last K chunk is multiplied (pays where C blocks have few
+ *          products; the kernel without it keeps fewer registers live).
  * The table maps the block edges present (A's rows, A's columns, B's
  * columns, each as a mask with bit e-1 set for edge e and bit 31 for every
  * edge >= 32) to a variant; a multiply whose masks have no entry uses 2 when
  * every inner edge is >= 16, else 0.  The vector form gives the same bits
- * with either tile policy; the matrix-core form adds in another order, within
+ * with either tile policy and with or without the prefetch; the matrix-core form adds in another order, within
  * FP64 rounding of the exact sum.
  *
  * bsmm_tune_mid computes C_out = alpha*A*B + beta*C_in exactly as

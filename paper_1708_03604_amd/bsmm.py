@@ -30,7 +30,7 @@ BSMM_PATH_SMALL = 2
 BSMM_PATH_SPLIT23 = 3
 BSMM_PATH_SLICE23 = 4
 BSMM_SMALL_VARIANTS = 8
-BSMM_MID_VARIANTS = 4
+BSMM_MID_VARIANTS = 8
 
 
 class BsmmError(RuntimeError):

@@ -330,7 +330,8 @@ ClassVariants tuned_variants(uint64_t key, int32_t edge) {
 
 // Tuning table of the generic path: edge masks (A's rows, A's columns, B's
 // columns) -> variant (bit 0: one 16x16 sub-tile for C blocks with both
-// edges <= 16; bit 1: the matrix-core form where every inner edge is >= 16).
+// edges <= 16; bit 1: the matrix-core form where every inner edge is >= 16;
+// bit 2: C_in loaded before each sub-tile's last chunk).
 using MidKey = std::array<uint32_t, 3>;
 std::map<MidKey, int32_t> g_tune_mid;
 
@@ -349,7 +350,7 @@ int32_t mid_variant(const bsmm_matrix* A, const bsmm_matrix* B) {
     auto it = g_tune_mid.find(mid_key(A, B));
     if (it != g_tune_mid.end()) v = it->second;
   }
-  return wide ? v : (v & 1);
+  return wide ? v : (v & ~2);
 }
 
 struct EventPair {
@@ -918,6 +919,7 @@ bsmm_status bsmm_multiply(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   const int32_t midv = mid_variant(A, B);
   na.wide_inner = (midv >> 1) & 1;
   na.mid_t16 = midv & 1;
+  na.mid_cpre = (midv >> 2) & 1;
   na.uniform = uniform;
   na.c_row_ptr = out.row_ptr.p;
   ClassVariants variants{-1, -1, -1, -1};
@@ -1341,6 +1343,7 @@ bsmm_status bsmm_tune_mid(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
     if ((v & 2) && !wide) continue;  // the matrix-core form needs inner edges >= 16: not timed
     na.wide_inner = (v >> 1) & 1;
     na.mid_t16 = v & 1;
+    na.mid_cpre = (v >> 2) & 1;
     HIP_TRY(hipEventRecord(ev.e[0], s));
     for (int32_t r = 0; r < reps; ++r) HIP_TRY(launch_numeric(na, 0, C->work.p, s));
     HIP_TRY(hipEventRecord(ev.e[1], s));
@@ -1355,6 +1358,7 @@ bsmm_status bsmm_tune_mid(double alpha, bsmm_mat A, bsmm_mat B, double beta, bsm
   }
   na.wide_inner = (best >> 1) & 1;
   na.mid_t16 = best & 1;
+  na.mid_cpre = (best >> 2) & 1;
   HIP_TRY(launch_numeric(na, 0, C->work.p, s));
   HIP_TRY(hipStreamSynchronize(s));
   {

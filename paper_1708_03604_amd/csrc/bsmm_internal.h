@@ -150,7 +150,8 @@ struct NumArgs {
   const int2* prod;
   double* c_values;
   int wide_inner;          // every inner block edge >= 16: the generic path may use the matrix-core form
-  int mid_t16;             // generic path: 16x16 sub-tiles for C blocks they pad less (tile policy 1)
+  int mid_t16;             // generic path: one 16x16 sub-tile for C blocks with both edges <= 16
+  int mid_cpre;            // generic path: load a sub-tile's C_in before its last chunk's multiply
   int uniform;             // common edge of every block of A and B, or 0
   // 23x23 paths: only the C blocks of rows [panel[0], panel[1]) are computed,
   // and prod holds that panel's products from index 0; nullptr = all

@@ -18,6 +18,10 @@ namespace bsmm {
 // product into K chunks of at most 32; a sub-tile is accumulated in registers
 // over all chunks of all products of its C block.
 //
+// C_in prefetch (g.mid_cpre, also chosen by the autotuner): the C_in values of
+// a sub-tile are loaded before its last chunk is multiplied (faster where C
+// blocks have few products, slower where the loop's registers matter more).
+//
 // Tile policy (g.mid_t16, chosen by the autotuner per set of block edges):
 // 0 = every C block in 32x32 sub-tiles; 1 = a C block with both edges <= 16
 // (e.g. 9x9 beside 22- and 32-edge blocks) is one 16x16 sub-tile, in the
@@ -118,7 +122,7 @@ __device__ __forceinline__ bool mid_next(const NumArgs& g, MidCursor& u, int32_t
 
 // WIDE: every inner block edge is >= 16 (the matrix-core form may run); the
 // other instantiation is the vector form alone.
-template <bool WIDE>
+template <bool WIDE, bool CPRE>
 __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
   __shared__ __align__(16) double lds[4][2 * kMidOperand];  // per wave: A^T, then B
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -209,12 +213,12 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
     stage(mma, t16);
     sync();
     const bool last = mid_next(g, f, nnzc, nwaves);
-    // The sub-tile ends with this chunk: load its C_in values now, before the
-    // next chunk's operand loads, so that they arrive during the multiply and
-    // waiting for them at the finish does not wait for the operand loads.
+    // CPRE: the sub-tile ends with this chunk, so load its C_in values now,
+    // before the next chunk's operand loads: they arrive during the multiply,
+    // and waiting for them at the finish does not wait for the operand loads
+    // (the form without it keeps fewer registers live through the loop).
     double cin[4][4];
-    const int64_t off = last ? g.c_blk_off[cur.c] : 0;
-    if (last) {
+    if (CPRE && last) {
       const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
       const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
 #pragma unroll
@@ -283,7 +287,9 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
     }
     if (last) {
       // alpha * acc + beta * C_in, then store the lane's 16 outputs
-      const bool old = g.use_old && g.c_old_idx[cur.c] >= 0;
+      const int64_t off = g.c_blk_off[cur.c];
+      const int32_t o = g.use_old ? g.c_old_idx[cur.c] : -1;
+      const double* ov = o >= 0 ? g.Cin.values + g.Cin.blk_off[o] : nullptr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -291,9 +297,10 @@ __global__ __launch_bounds__(256, 2) void k_numeric_mid(NumArgs g) {
           const int r = cur.t * cur.ti + (mma ? 8 * i + 4 * ((lane >> 3) & 1) + (lane >> 4) : t16 ? 2 * ty + i : 4 * ty + i);
           const int cc = cur.t * cur.tj + (mma ? 8 * j + 4 * ((lane >> 2) & 1) + (lane & 3) : t16 ? 2 * tx + j : 4 * tx + j);
           if ((!t16 || (i < 2 && j < 2)) && r < cur.m && cc < cur.n) {
+            const int64_t e = (int64_t)r * cur.n + cc;
             double v = g.alpha * acc[i][j];
-            if (old) v = v + g.beta * cin[i][j];
-            g.c_values[off + (int64_t)r * cur.n + cc] = v;
+            if (ov) v = v + g.beta * (CPRE ? cin[i][j] : ov[e]);
+            g.c_values[off + e] = v;
           }
           acc[i][j] = 0.0;
         }
@@ -669,10 +676,17 @@ hipError_t launch_numeric(const NumArgs& a, int uniform_size, int32_t* work, hip
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t blocks = (a.nnzc_bound + 3) / 4;  // every wave owns at least one C block at the start
   if (blocks > 2 * cus) blocks = 2 * cus;   // two workgroups of 4 waves per CU stay resident
-  if (a.wide_inner)
-    hipLaunchKernelGGL(k_numeric_mid<true>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_numeric_mid<false>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  if (a.wide_inner) {
+    if (a.mid_cpre)
+      hipLaunchKernelGGL((k_numeric_mid<true, true>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_numeric_mid<true, false>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  } else {
+    if (a.mid_cpre)
+      hipLaunchKernelGGL((k_numeric_mid<false, true>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_numeric_mid<false, false>), dim3((uint32_t)blocks), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -1,13 +1,15 @@
 """Tile shapes and forms of the generic path and its autotuner, through the C-ABI.
 
-The generic path (block sizes neither all <= 16 nor all 23x23) has four
+The generic path (block sizes neither all <= 16 nor all 23x23) has eight
 variants: 32x32 sub-tiles or, for C blocks with both edges <= 16, one 16x16
 sub-tile, on the FP64 vector units or, for 32x32 sub-tiles of C blocks with
-both edges >= 16 when every inner edge is >= 16, on the FP64 matrix cores.  Every variant must give the
+both edges >= 16 when every inner edge is >= 16, on the FP64 matrix cores;
+each with or without C_in loaded ahead of a sub-tile's last chunk.  Every variant must give the
 oracle's pattern and product stack exactly and its values within the FP64
 tolerance; integer inputs exactly.  The vector form sums every output over the
-same inner indices in the same order with either tile size, so variants 0 and
-1 must give identical bits.  The tuner must leave C as a plain multiply with
+same inner indices in the same order with either tile size and either C_in
+load, so variants 0, 1, 4 and 5 must give identical bits, and so must 2 and 6,
+3 and 7.  The tuner must leave C as a plain multiply with
 its chosen variant does and enter that variant into the table.
 """
 import numpy as np
@@ -99,21 +101,26 @@ def test_every_variant_matches_the_oracle(table, name):
     A, B, Co = operands(name, 931)
     eps = 0.05
     ref = oracle.multiply(0.75, A, B, -0.5, Co, eps)
-    allowed = range(bsmm.BSMM_MID_VARIANTS) if wide_inner(SETS[name][1]) else (0, 1)
+    allowed = range(bsmm.BSMM_MID_VARIANTS) if wide_inner(SETS[name][1]) else (0, 1, 4, 5)
     vals = {}
     for v in allowed:
         out = run(A, B, Co, v, 0.75, -0.5, eps)
         check(ref, out, v, exact=False)
         vals[v] = out[2]
-    # the vector form gives the same bits with 16x16 and 32x32 sub-tiles
-    assert np.array_equal(vals[0], vals[1])
+    # the vector form gives the same bits with 16x16 and 32x32 sub-tiles and
+    # with or without the C_in prefetch; so does each matrix-core variant
+    for v in (1, 4, 5):
+        assert np.array_equal(vals[0], vals[v])
+    for v in (2, 3):
+        if v in vals:
+            assert np.array_equal(vals[v], vals[v + 4])
 
 
 @pytest.mark.parametrize("name", sorted(SETS))
 def test_every_variant_exact_on_integers(table, name):
     A, B, Co = operands(name, 951, kind="int")
     ref = oracle.multiply(1.0, A, B, 2.0, Co, 0.0)
-    allowed = range(bsmm.BSMM_MID_VARIANTS) if wide_inner(SETS[name][1]) else (0, 1)
+    allowed = range(bsmm.BSMM_MID_VARIANTS) if wide_inner(SETS[name][1]) else (0, 1, 4, 5)
     for v in allowed:
         check(ref, run(A, B, Co, v, 1.0, 2.0, 0.0), v, exact=True)
 
@@ -121,7 +128,7 @@ def test_every_variant_exact_on_integers(table, name):
 def test_matrix_core_bit_dropped_for_narrow_inner_edges(table):
     A, B, Co = operands("mixed_9_22_32", 961)
     ref = oracle.multiply(1.0, A, B, 1.0, Co, 0.0)
-    for v, used in ((2, 0), (3, 1)):
+    for v, used in ((2, 0), (3, 1), (6, 4), (7, 5)):
         check(ref, run(A, B, Co, v, 1.0, 1.0, 0.0), used, exact=False)
 
 
@@ -147,7 +154,7 @@ def test_tuner_result_and_table(table):
     dN, dK, dQ = bsmm.Matrix.from_csr(N), bsmm.Matrix.from_csr(K), bsmm.Matrix.from_csr(Q)
     dE = bsmm.Matrix.empty(N.row_sizes, K.col_sizes)
     v2, ms2 = bsmm.bsmm_tune_mid(1.0, dN.handle, dK.handle, 1.0, dQ.handle, dE.handle, 0.0, 1)
-    assert v2 in (0, 1) and (ms2[:2] > 0).all() and not ms2[2:].any()
+    assert v2 in (0, 1, 4, 5) and all(ms2[u] > 0 for u in (0, 1, 4, 5)) and not ms2[[2, 3, 6, 7]].any()
     for m in (dA, dB, dCin, dC, dD, dN, dK, dQ, dE):
         m.close()
 
